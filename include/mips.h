@@ -1,0 +1,204 @@
+/*
+ * mips.h -- C ABI of libmips: exact batch top-K maximum inner product search
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper Section II-A, "Problem Statement: Batch Exact MIPS"):
+ * given user vectors U (n_u x f) and item vectors I (n_i x f), return for
+ * every user the K items with the largest inner product u.i.
+ *
+ * Result contract (identical for every entry point and every precision):
+ *   key(u, i)  = the float64 value of  acc <- +0; for j = 0..f-1:
+ *                acc <- RN64(acc + (double)U[u,j] * (double)I[i,j])
+ *                (each float32 x float32 product is exact in float64, so the
+ *                 left-to-right order of the additions is the only choice);
+ *   top-K(u)   = the first K items when all items are ordered by
+ *                (key descending, item index ascending).
+ * out_idx[u*K + k] is the k-th item of top-K(u) and out_score[u*K + k] its
+ * key.  The paper computes ratings in double precision and leaves the
+ * summation order and the tie rule open; this library fixes both as above so
+ * that exactly one answer is correct.
+ *
+ * Precision: the bulk of the scoring runs on the matrix cores in float32,
+ * bfloat16 or OCP E4M3 (per-row power-of-two scaled), always with float32
+ * accumulation.  Each screened score s carries a rigorous error bound e with
+ * s - e <= key <= s + e; every item whose upper bound reaches the running
+ * K-th best lower bound is kept and only those are rescored in float64.  The
+ * precision therefore changes speed, never the answer.
+ *
+ * Conventions for every function below:
+ *  - Array pointers are DEVICE pointers owned by the caller, row-major and
+ *    contiguous (float32 unless stated).  The library never frees them and
+ *    keeps none of them after the call returns (the Maximus index copies
+ *    what it needs).
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All work
+ *    is enqueued on it and the call returns without synchronising, unless
+ *    `stats` is non-NULL: then the call synchronises the stream and fills
+ *    `stats` (host memory).
+ *  - Argument errors are reported before anything is enqueued.  No C++
+ *    exception crosses this interface.  Return values are mips_status codes
+ *    (0 on success, negative on failure); mips_last_error_message() gives a
+ *    thread-local description of the most recent failure.
+ *  - Non-finite inputs are detected on the device.  They are reported as
+ *    MIPS_ERR_NONFINITE only when `stats` forces a synchronisation (and in
+ *    stats->nonfinite_input); the outputs are then unspecified.
+ *  - Calls that share a workspace must not overlap in time (different
+ *    streams need different workspaces).
+ */
+#ifndef MIPS_H
+#define MIPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MIPS_OK = 0,
+    MIPS_ERR_ARG = -1,          /* bad argument; nothing was enqueued                 */
+    MIPS_ERR_NONFINITE = -2,    /* NaN or Inf in U or I (reported only with stats)    */
+    MIPS_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed         */
+    MIPS_ERR_WORKSPACE = -4,    /* workspace NULL or smaller than *_workspace_size()  */
+    MIPS_ERR_NOMEM = -5,        /* the library could not allocate (Maximus index)     */
+    MIPS_ERR_UNSUPPORTED = -6   /* valid request outside what this build supports     */
+} mips_status;
+
+typedef enum {
+    MIPS_PREC_FP32 = 0,         /* float32 matrix-core screen                          */
+    MIPS_PREC_BF16 = 1,         /* bfloat16 (round-to-nearest-even) screen             */
+    MIPS_PREC_FP8_E4M3 = 2      /* OCP E4M3 screen with per-row power-of-two scales    */
+} mips_precision;
+
+/* Host-side counters of one call; filled only when a non-NULL pointer is passed. */
+typedef struct {
+    int64_t candidates_total;        /* (user, item) pairs the screen kept for certification     */
+    int64_t candidates_max_per_user; /* largest per-user candidate count                           */
+    int64_t rescored_pairs;          /* pairs rescored in float64 after certification              */
+    int64_t overflow_users;          /* users finished on the exact fallback path                  */
+    int64_t items_scored;            /* (user, item) pairs scored by the screen (unpadded)          */
+    double  mean_items_visited;      /* mean items scored per user (n_i for brute force)            */
+    double  max_screen_abs_err;      /* max |screened score - key| over rescored pairs              */
+    double  max_screen_rel_err;      /* same, divided by ||u|| ||i||                                 */
+    int32_t nonfinite_input;         /* 1 if U or I held NaN or Inf                                 */
+    int32_t reserved;
+} mips_stats;
+
+/* ------------------------------------------------------------------------- *
+ * Brute force: blocked matrix multiply fused with a per-user streaming top-K
+ * (paper Section II-B, "Blocked Matrix Multiply").  The score matrix U I^T is
+ * produced tile by tile on the matrix cores and never written to memory.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace mips_bmm_topk needs for these sizes (0 if the
+ * sizes are invalid).  Does not touch the GPU. */
+size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t K,
+                                    int32_t precision);
+
+/* Top-K of every user.
+ *   U          n_u x f float32 (device)        I      n_i x f float32 (device)
+ *   K          1 <= K <= n_i; K <= 4096 (larger: MIPS_ERR_UNSUPPORTED)
+ *   precision  a mips_precision value
+ *   out_idx    n_u x K int32 (device, written)  out_score n_u x K float64 (device, written)
+ *   workspace  device buffer of at least mips_bmm_topk_workspace_size() bytes,
+ *              256-byte aligned, owned by the caller; contents on entry ignored
+ * Limits: 1 <= n_u, 1 <= n_i < 2^31, 1 <= f <= 256.  Fast screening paths
+ * cover K <= 64 and f <= 128; other valid requests run on the exact float64
+ * fallback kernel (same result, slower). */
+int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
+                  int32_t precision, int32_t* out_idx, double* out_score,
+                  void* workspace, size_t workspace_bytes, void* stream, mips_stats* stats);
+
+/* ------------------------------------------------------------------------- *
+ * Maximus (paper Section III, Algorithm 1): k-means over users
+ * (Section III-A), per cluster the largest user-centroid angle theta_b and
+ * every item ordered by the bound of Eq. (appx_bound)
+ * ||i|| cos(max(theta_ic - theta_b, 0)) (Section III-B, ConstructIndex), then
+ * per user a walk down its cluster's list in item blocks shared by the
+ * cluster's users (Section III-D), stopping once ||u|| times the bound of the
+ * next item is below the K-th best score (Section III-C, QueryIndex).
+ * ------------------------------------------------------------------------- */
+typedef struct mips_maximus_index mips_maximus_index; /* opaque; owns device memory */
+
+/* Build the index.
+ *   n_clusters   1 <= C <= min(n_u, 4096)   kmeans_iters  0 <= iters <= 100 Lloyd updates
+ *   seed         picks the C initial centroids (Forgy initialisation)
+ *   block_items  0 = default; otherwise the number of leading list items scored for
+ *                every user of a cluster before any may stop (the paper's B), rounded up
+ *                to the item tile (32)
+ *   out_index    receives the index; free it with mips_maximus_free()
+ * The index copies U and I (and their screen copies); the caller may free them
+ * afterwards.  Synchronises `stream` before returning (the index records sizes
+ * computed on the device).  Returns MIPS_ERR_NOMEM if device memory runs out. */
+int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f,
+                       int32_t n_clusters, int32_t kmeans_iters, uint64_t seed,
+                       int32_t block_items, void* stream, mips_maximus_index** out_index);
+
+/* Workspace bytes for mips_maximus_query (0 on bad arguments). */
+size_t mips_maximus_query_workspace_size(const mips_maximus_index* index, int32_t K,
+                                         int32_t precision);
+
+/* Top-K of every user of the index, same contract and output as mips_bmm_topk
+ * (out_idx / out_score are n_u x K in the original user order).  Read-only on
+ * the index: concurrent queries with separate workspaces are allowed.
+ * stats->mean_items_visited reports the mean walk length w-bar of Eq. (runtime). */
+int mips_maximus_query(const mips_maximus_index* index, int32_t K, int32_t precision,
+                       int32_t* out_idx, double* out_score, void* workspace,
+                       size_t workspace_bytes, void* stream, mips_stats* stats);
+
+/* Release the index and its device memory (NULL is ignored). */
+void mips_maximus_free(mips_maximus_index* index);
+
+/* Index description, for tests and reports (host memory, NULL fields skipped).
+ * centroids C x f float64, theta_b C float64, assign n_u int32,
+ * lists C x n_i int32 (item indices in walk order), bounds C x n_i float32
+ * (the rounded-up bound of each list entry, in walk order).
+ * Synchronises `stream`. */
+int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, int32_t* f,
+                        int64_t* n_u, int64_t* n_i, double* centroids, double* theta_b,
+                        int32_t* assign, int32_t* lists, float* bounds, void* stream);
+
+/* ------------------------------------------------------------------------- *
+ * Backward of a loss on the top-K scores (not in the paper).  With the top-K
+ * indices fixed, S[u,k] = U[u] . I[idx[u,k]] and G = dL/dS:
+ *   dU[u]  = sum_k G[u,k] I[idx[u,k]]                      (gather)
+ *   dI[i]  = sum over (u,k) with idx[u,k] = i of G[u,k] U[u]  (scatter-add)
+ * dU (n_u x f) and dI (n_i x f) are overwritten.  dU is deterministic; dI is
+ * accumulated with float32 atomics, so its last bits may vary run to run.
+ * idx entries must lie in [0, n_i) (checked on the device; a bad index makes
+ * the call's stats-free return value MIPS_OK but is skipped and counted).
+ * ------------------------------------------------------------------------- */
+int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
+                       int32_t K, const int32_t* idx, const float* grad_scores, float* dU,
+                       float* dI, void* stream);
+
+/* ------------------------------------------------------------------------- *
+ * Diagnostics.
+ * ------------------------------------------------------------------------- */
+const char* mips_status_string(int status);
+const char* mips_last_error_message(void);
+
+/* Kernel timing.  While enabled, every kernel phase launched by this library
+ * is bracketed by HIP events recorded on the caller's stream (no host
+ * synchronisation).  mips_profile_read() waits for the recorded events, adds
+ * their durations into `ms` and `launches` (arrays of MIPS_PROFILE_PHASES,
+ * indexed by mips_profile_phase) and clears the record. */
+typedef enum {
+    MIPS_PHASE_ITEM_PREP = 0,   /* item norms, screen copies, norm order, packing   */
+    MIPS_PHASE_SCREEN = 1,      /* matrix-core score tiles + streaming top-K          */
+    MIPS_PHASE_CERTIFY = 2,     /* certification + float64 rescore + final order      */
+    MIPS_PHASE_FALLBACK = 3,    /* exact float64 path for flagged users               */
+    MIPS_PHASE_BUILD = 4,       /* Maximus index construction                         */
+    MIPS_PHASE_WALK = 5,        /* Maximus blocked walk (screen over list blocks)     */
+    MIPS_PHASE_BACKWARD = 6,    /* dU gather + dI scatter                             */
+    MIPS_PROFILE_PHASES = 7
+} mips_profile_phase;
+
+int mips_profile_enable(int enable);
+int mips_profile_read(double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIPS_H */

@@ -1,0 +1,390 @@
+// C ABI of libmips (declared in include/mips.h): argument checks, launch
+// plans, workspace carving, kernel sequencing, statistics and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/mips.h"
+#include "internal.h"
+
+namespace mips {
+
+// ---------------------------------------------------------------------------
+// Errors.
+// ---------------------------------------------------------------------------
+static thread_local char g_msg[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(MIPS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing: event pairs recorded on the caller's stream.
+// ---------------------------------------------------------------------------
+struct PhaseRecord {
+    int phase;
+    hipEvent_t start, stop;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<PhaseRecord> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+
+static hipEvent_t pool_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+PhaseTimer::PhaseTimer(int phase, hipStream_t s) : phase_(phase), stream_(s) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    start_ = pool_event();
+    stop_ = pool_event();
+    if (start_ && stop_ && hipEventRecord(start_, s) == hipSuccess) active_ = true;
+}
+
+PhaseTimer::~PhaseTimer() {
+    if (!active_) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (hipEventRecord(stop_, stream_) == hipSuccess)
+        g_prof_pending.push_back({phase_, start_, stop_});
+}
+
+// ---------------------------------------------------------------------------
+// Plans and workspace layout.
+// ---------------------------------------------------------------------------
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t, ScreenPlan* out) {
+    ScreenPlan p;
+    p.prec = prec;
+    p.f = f;
+    p.K = K;
+    p.n_u = n_u;
+    p.n_i = n_i;
+    p.fast = (K <= 64 && f <= 128);
+    if (prec == PREC_FP32) {
+        p.f_pad = (f + 1) & ~1;
+        p.nch = p.f_pad / 2;
+        p.NCH = p.nch <= 8 ? 8 : (p.nch <= 32 ? 32 : 64);
+    } else if (prec == PREC_BF16) {
+        p.f_pad = (f + 15) & ~15;
+        p.nch = p.f_pad / 16;
+        p.NCH = p.nch <= 2 ? 2 : (p.nch <= 4 ? 4 : 8);
+    } else {
+        p.f_pad = (f + 63) & ~63;
+        p.nch = p.f_pad / 64;
+        p.NCH = p.nch <= 1 ? 1 : 2;
+    }
+    p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64)));
+    p.UB = ub_for(prec, p.KM, p.NCH);
+    if (prec == PREC_FP8)
+        p.cap = std::max(256, 4 * p.KM + 64);
+    else
+        p.cap = std::max(64, 2 * p.KM + 32);
+    p.kc = p.cap;
+    p.n_blk = (n_i + 31) / 32;
+    p.n_i_pad = p.n_blk * 32;
+    p.n_waves = (n_u + 32 * p.UB - 1) / (32 * p.UB);
+    p.n_ublk = p.n_waves * p.UB;
+    p.fb_grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_u));
+    const double n = (prec == PREC_FP32) ? (double)(p.f_pad + 1) : (double)p.f_pad;
+    const double g = n * 0x1p-22 / (1.0 - n * 0x1p-22);
+    p.gamma = (float)(g * (1.0 + 0x1p-20));
+    *out = p;
+    return true;
+}
+
+struct BmmLayout {
+    size_t ctrl, hist, uflag, zero_end;
+    size_t flist, uscal, bucket, perm, Corig, Gorig, Eorig, kexp, qrow, packed, pscale, blockmax;
+    size_t cnt, cand, fbkeys, total;
+};
+
+static BmmLayout bmm_layout(const ScreenPlan& p) {
+    BmmLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += al256(b); return r; };
+    const size_t esz = p.prec == PREC_FP32 ? 4 : (p.prec == PREC_BF16 ? 2 : 1);
+    L.ctrl = take(sizeof(Ctrl));
+    L.hist = take(2 * kBuckets * sizeof(unsigned int));
+    L.uflag = take((size_t)p.n_u * 4);
+    L.zero_end = o;
+    L.flist = take((size_t)p.n_u * 4);
+    L.uscal = take((size_t)p.n_u * 16);
+    if (p.fast) {
+        L.bucket = take((size_t)p.n_i * 4);
+        L.perm = take((size_t)p.n_i_pad * 4);
+        L.Corig = take((size_t)p.n_i * 4);
+        L.Gorig = take((size_t)p.n_i * 4);
+        L.Eorig = take((size_t)p.n_i * 4);
+        L.kexp = take((size_t)p.n_i * 4);
+        L.qrow = take((size_t)p.n_i * p.f_pad * esz);
+        L.packed = take((size_t)p.n_i_pad * p.f_pad * esz);
+        L.pscale = take((size_t)p.n_i_pad * 4);
+        L.blockmax = take((size_t)p.n_blk * 8);
+        L.cnt = take((size_t)p.n_ublk * 64 * 4);
+        L.cand = take((size_t)p.n_ublk * p.cap * 64 * 8);
+    }
+    L.fbkeys = take((size_t)p.fb_grid * p.n_i * 8);
+    L.total = o;
+    return L;
+}
+
+static int check_common(int64_t n_u, int64_t n_i, int f, int K, int prec) {
+    if (n_u < 1) return fail(MIPS_ERR_ARG, "n_u must be >= 1 (got %lld)", (long long)n_u);
+    if (n_i < 1 || n_i >= ((int64_t)1 << 31))
+        return fail(MIPS_ERR_ARG, "n_i must be in [1, 2^31) (got %lld)", (long long)n_i);
+    if (n_u >= ((int64_t)1 << 31)) return fail(MIPS_ERR_ARG, "n_u must be < 2^31");
+    if (f < 1 || f > 256) return fail(MIPS_ERR_ARG, "f must be in [1, 256] (got %d)", f);
+    if (K < 1 || (int64_t)K > n_i) return fail(MIPS_ERR_ARG, "K must be in [1, n_i] (got %d)", K);
+    if (prec < PREC_FP32 || prec > PREC_FP8) return fail(MIPS_ERR_ARG, "unknown precision %d", prec);
+    if (K > kFallbackMaxK)
+        return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported (got %d)", kFallbackMaxK, K);
+    return MIPS_OK;
+}
+
+static int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stats* stats) {
+    Ctrl h{};
+    hipError_t e = hipMemcpyAsync(&h, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading statistics");
+    std::memset(stats, 0, sizeof(*stats));
+    stats->candidates_total = (int64_t)h.cand_total;
+    stats->candidates_max_per_user = (int64_t)h.cand_max;
+    stats->rescored_pairs = (int64_t)h.rescored;
+    stats->overflow_users = (int64_t)h.fb_count;
+    stats->items_scored = (int64_t)h.visited;
+    stats->mean_items_visited = n_u > 0 ? (double)h.visited / (double)n_u : 0.0;
+    double d;
+    std::memcpy(&d, &h.max_abs_err, 8);
+    stats->max_screen_abs_err = d;
+    std::memcpy(&d, &h.max_rel_err, 8);
+    stats->max_screen_rel_err = d;
+    stats->nonfinite_input = h.nonfinite ? 1 : 0;
+    (void)n_i;
+    if (h.nonfinite) return fail(MIPS_ERR_NONFINITE, "U or I holds NaN or Inf");
+    return MIPS_OK;
+}
+
+}  // namespace mips
+
+using namespace mips;
+
+extern "C" {
+
+const char* mips_status_string(int status) {
+    switch (status) {
+        case MIPS_OK: return "MIPS_OK";
+        case MIPS_ERR_ARG: return "MIPS_ERR_ARG";
+        case MIPS_ERR_NONFINITE: return "MIPS_ERR_NONFINITE";
+        case MIPS_ERR_HIP: return "MIPS_ERR_HIP";
+        case MIPS_ERR_WORKSPACE: return "MIPS_ERR_WORKSPACE";
+        case MIPS_ERR_NOMEM: return "MIPS_ERR_NOMEM";
+        case MIPS_ERR_UNSUPPORTED: return "MIPS_ERR_UNSUPPORTED";
+        default: return "MIPS_ERR_UNKNOWN";
+    }
+}
+
+const char* mips_last_error_message(void) { return g_msg; }
+
+int mips_profile_enable(int enable) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = enable != 0;
+    return MIPS_OK;
+}
+
+int mips_profile_read(double* ms, int64_t* launches) {
+    std::vector<PhaseRecord> recs;
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        recs.swap(g_prof_pending);
+    }
+    int rc = MIPS_OK;
+    for (auto& r : recs) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "profile event");
+        } else if (r.phase >= 0 && r.phase < MIPS_PROFILE_PHASES) {
+            if (ms) ms[r.phase] += (double)t;
+            if (launches) launches[r.phase] += 1;
+        }
+    }
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& r : recs) {
+        g_prof_pool.push_back(r.start);
+        g_prof_pool.push_back(r.stop);
+    }
+    return rc;
+}
+
+size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t K,
+                                    int32_t precision) {
+    if (check_common(n_u, n_i, f, K, precision) != MIPS_OK) return 0;
+    ScreenPlan p;
+    make_screen_plan(n_u, n_i, f, K, precision, 0, &p);
+    return bmm_layout(p).total;
+}
+
+int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
+                  int32_t precision, int32_t* out_idx, double* out_score, void* workspace,
+                  size_t workspace_bytes, void* stream, mips_stats* stats) {
+    int rc = check_common(n_u, n_i, f, K, precision);
+    if (rc != MIPS_OK) return rc;
+    if (!U || !I || !out_idx || !out_score) return fail(MIPS_ERR_ARG, "null array pointer");
+    ScreenPlan p;
+    make_screen_plan(n_u, n_i, f, K, precision, 0, &p);
+    const BmmLayout L = bmm_layout(p);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", L.total, workspace_bytes);
+    if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    Ctrl* ctrl = (Ctrl*)(ws + L.ctrl);
+    hipError_t e;
+
+    {
+        PhaseTimer t(MIPS_PHASE_ITEM_PREP, s);
+        if ((e = launch_zero(ws, L.zero_end, s)) != hipSuccess) return hip_fail(e, "zero");
+        if (p.fast) {
+            ItemPrepArgs ia{};
+            ia.I = I;
+            ia.n_i = n_i;
+            ia.n_blk = p.n_blk;
+            ia.f = f;
+            ia.f_pad = p.f_pad;
+            ia.nch = p.nch;
+            ia.gamma = p.gamma;
+            ia.Corig = (float*)(ws + L.Corig);
+            ia.Gorig = (float*)(ws + L.Gorig);
+            ia.Eorig = (float*)(ws + L.Eorig);
+            ia.kexp = (int*)(ws + L.kexp);
+            ia.qrow = ws + L.qrow;
+            ia.bucket = (int*)(ws + L.bucket);
+            ia.hist = (unsigned int*)(ws + L.hist);
+            ia.perm = (int*)(ws + L.perm);
+            ia.packed = ws + L.packed;
+            ia.pscale = (int*)(ws + L.pscale);
+            ia.blockmax = (float2*)(ws + L.blockmax);
+            ia.ctrl = ctrl;
+            if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
+                return hip_fail(e, "item preparation");
+        } else {
+            if ((e = launch_nonfinite_scan(U, n_u * f, I, n_i * f, ctrl, s)) != hipSuccess)
+                return hip_fail(e, "finite check");
+        }
+    }
+    ScreenArgs a{};
+    a.U = U;
+    a.I = I;
+    a.n_u = n_u;
+    a.n_i = n_i;
+    a.n_blk = p.n_blk;
+    a.n_i_pad = p.n_i_pad;
+    a.f = f;
+    a.f_pad = p.f_pad;
+    a.nch = p.nch;
+    a.K = K;
+    a.cap = p.cap;
+    a.kc = p.kc;
+    a.gamma = p.gamma;
+    a.ctrl = ctrl;
+    a.uflag = (int*)(ws + L.uflag);
+    a.flist = (int*)(ws + L.flist);
+    a.uscal = (float4*)(ws + L.uscal);
+    a.out_idx = out_idx;
+    a.out_score = out_score;
+    if (p.fast) {
+        a.packed = ws + L.packed;
+        a.pscale = (const int*)(ws + L.pscale);
+        a.blockmax = (const float2*)(ws + L.blockmax);
+        a.perm = (const int*)(ws + L.perm);
+        a.qrow = ws + L.qrow;
+        a.kexp = (const int*)(ws + L.kexp);
+        a.Corig = (const float*)(ws + L.Corig);
+        a.Gorig = (const float*)(ws + L.Gorig);
+        a.cnt = (int*)(ws + L.cnt);
+        a.cand = (int2*)(ws + L.cand);
+        {
+            PhaseTimer t(MIPS_PHASE_SCREEN, s);
+            if ((e = launch_screen(p, a, s)) != hipSuccess) return hip_fail(e, "screen");
+        }
+        {
+            PhaseTimer t(MIPS_PHASE_CERTIFY, s);
+            if ((e = launch_certify(p, a, s)) != hipSuccess) return hip_fail(e, "certify");
+        }
+    } else {
+        if ((e = launch_flag_all(n_u, a.uflag, a.flist, ctrl, s)) != hipSuccess)
+            return hip_fail(e, "flag all");
+    }
+    {
+        PhaseTimer t(MIPS_PHASE_FALLBACK, s);
+        FallbackArgs fa{};
+        fa.U = U;
+        fa.I = I;
+        fa.n_u = n_u;
+        fa.n_i = n_i;
+        fa.f = f;
+        fa.K = K;
+        fa.flist = a.flist;
+        fa.ctrl = ctrl;
+        fa.keys = (double*)(ws + L.fbkeys);
+        fa.out_idx = out_idx;
+        fa.out_score = out_score;
+        if ((e = launch_fallback(p, fa, s)) != hipSuccess) return hip_fail(e, "fallback");
+    }
+    if (stats) {
+        rc = finish_stats(ctrl, s, n_u, n_i, stats);
+        if (rc == MIPS_OK && !p.fast) stats->items_scored = n_u * n_i, stats->mean_items_visited = (double)n_i;
+        return rc;
+    }
+    return MIPS_OK;
+}
+
+}  // extern "C"
+
+// Entry points implemented in later stages of the library.
+extern "C" {
+
+int mips_maximus_build(const float*, int64_t, const float*, int64_t, int32_t, int32_t, int32_t,
+                       uint64_t, int32_t, void*, mips_maximus_index** out_index) {
+    if (out_index) *out_index = nullptr;
+    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
+}
+size_t mips_maximus_query_workspace_size(const mips_maximus_index*, int32_t, int32_t) { return 0; }
+int mips_maximus_query(const mips_maximus_index*, int32_t, int32_t, int32_t*, double*, void*, size_t,
+                       void*, mips_stats*) {
+    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
+}
+void mips_maximus_free(mips_maximus_index*) {}
+int mips_maximus_export(const mips_maximus_index*, int32_t*, int32_t*, int64_t*, int64_t*, double*,
+                        double*, int32_t*, int32_t*, float*, void*) {
+    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
+}
+int mips_topk_backward(const float*, const float*, int64_t, int64_t, int32_t, int32_t,
+                       const int32_t*, const float*, float*, float*, void*) {
+    return fail(MIPS_ERR_UNSUPPORTED, "backward is not built yet");
+}
+
+}  // extern "C"

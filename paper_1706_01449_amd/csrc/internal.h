@@ -1,0 +1,162 @@
+// Internal declarations of libmips shared by the host-side files: the
+// device control block, the launch plans and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mips {
+
+// Precision codes (same values as the public mips_precision enum).
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
+
+// User blocks of 32 per screen wave: fewer when the register K-list (KM
+// entries per user block) or the float32 operands (NCH registers per user
+// block) grow.
+__host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap) {
+    return prec == PREC_FP32 ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
+                             : (km <= 16 ? 4 : (km == 32 ? 2 : 1));
+}
+
+// Device-resident control block of one call.  Zeroed at the start of every
+// call by a fill kernel (never by a memset node, so callers may capture the
+// call in a graph).
+struct Ctrl {
+    unsigned int nonfinite;          // any NaN/Inf seen in U or I
+    unsigned int fb_count;           // users appended to the fallback list
+    unsigned int cmax_bits;          // max_i ||i|| (rounded up), float bits
+    unsigned int emax_bits;          // max_i ||screen(i)||, float bits
+    unsigned int gmax_bits;          // max_i G_i, float bits
+    unsigned int bad_index;          // backward: idx entries out of range
+    unsigned long long cand_total;   // candidates appended by the screen
+    unsigned long long cand_max;     // max candidates of one user
+    unsigned long long rescored;     // pairs rescored in float64
+    unsigned long long visited;      // items scored, summed over users
+    unsigned long long max_abs_err;  // float64 bits of max |s - key|
+    unsigned long long max_rel_err;  // float64 bits of max |s - key| / (||u|| ||i||)
+};
+
+// Shape of the screen for one call.
+struct ScreenPlan {
+    int prec = 0;
+    int f = 0, f_pad = 0, nch = 0;   // factors, padded factors, matrix-core K-chunks
+    int K = 0, KM = 0, UB = 0;       // K, register K-list length, user blocks per wave
+    int NCH = 0;                     // compiled chunk capacity (>= nch)
+    int cap = 0;                     // candidate slots per lane
+    int kc = 0;                      // kept-candidate slots per lane in certification
+    bool fast = false;               // false: every user goes to the exact fallback kernel
+    int64_t n_u = 0, n_i = 0;
+    int64_t n_blk = 0, n_i_pad = 0;  // item tiles of 32, padded item count
+    int64_t n_waves = 0;             // waves of the screen / certification grid
+    int64_t n_ublk = 0;              // n_waves * UB
+    int fb_grid = 0;                 // workgroups of the fallback kernel
+    float gamma = 0.0f;              // accumulation error factor of the screen
+};
+
+// Parameters shared by the screen (score tiles + streaming top-K) kernel and
+// the certification kernel.  `walk` selects the Maximus list walk.
+struct ScreenArgs {
+    const float* U;
+    const float* I;
+    int64_t n_u, n_i, n_blk, n_i_pad;
+    int f, f_pad, nch, K, cap, kc;
+    float gamma;
+    // brute force: items in norm order, packed in matrix-core operand order
+    const void* packed;
+    const int* pscale;        // FP8: E8M0 scale byte per sorted position
+    const float2* blockmax;   // per item tile: (max C, max G)
+    const int* perm;          // sorted position -> item index
+    // Maximus walk
+    int walk;
+    int shared_blocks;        // leading list tiles scored before any user may stop
+    const int4* tiles;        // (cluster, first sorted user, user count, 0)
+    const int* sorted_users;  // users grouped by cluster
+    const int* lists;         // C x n_i item indices in walk order
+    const float* lbound;      // C x n_i_pad rounded-up bounds in walk order (+ -inf pad)
+    const float2* cblockmax;  // C x n_blk per-tile maxima in walk order
+    const void* qrow;         // n_i x f_pad screen copies by item index
+    const int* kexp;          // FP8: row scale exponent by item index
+    // per-item scalars by item index
+    const float* Corig;       // ||i|| rounded up
+    const float* Gorig;       // ||i - screen(i)|| + gamma ||screen(i)||, rounded up
+    // per-call state
+    Ctrl* ctrl;
+    int* uflag;               // n_u: 0 normal, 1 on the fallback list
+    int* flist;               // n_u: fallback list
+    float4* uscal;            // n_u: (A_u, B_u, slack_u, tau_u)
+    int* cnt;                 // n_ublk * 64 candidate counts
+    int2* cand;               // n_ublk * cap * 64 candidates (score bits, position)
+    int32_t* out_idx;
+    double* out_score;
+};
+
+struct FallbackArgs {
+    const float* U;
+    const float* I;
+    int64_t n_u, n_i;
+    int f, K;
+    const int* flist;
+    Ctrl* ctrl;
+    double* keys;             // fb_grid x n_i scratch
+    int32_t* out_idx;
+    double* out_score;
+};
+
+struct ItemPrepArgs {
+    const float* I;
+    int64_t n_i, n_blk;
+    int f, f_pad, nch;
+    float gamma;
+    float* Corig;
+    float* Gorig;
+    float* Eorig;
+    int* kexp;
+    void* qrow;
+    int* bucket;
+    unsigned int* hist;       // 4096 bucket counts, then 4096 offsets
+    int* perm;
+    void* packed;
+    int* pscale;
+    float2* blockmax;
+    Ctrl* ctrl;
+};
+
+constexpr int kBuckets = 4096;
+constexpr int kFallbackMaxK = 4096;
+
+// Launchers (each returns hipSuccess or the launch error).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s);
+hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s);
+
+hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
+                                 int64_t ni_elems, Ctrl* ctrl, hipStream_t s);
+
+// Host-side helpers of the C ABI.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// Brackets the kernels launched in its scope with HIP events on `s` while
+// kernel timing is enabled (mips_profile_enable); otherwise does nothing.
+class PhaseTimer {
+public:
+    PhaseTimer(int phase, hipStream_t s);
+    ~PhaseTimer();
+    PhaseTimer(const PhaseTimer&) = delete;
+    PhaseTimer& operator=(const PhaseTimer&) = delete;
+private:
+    int phase_;
+    hipStream_t stream_;
+    hipEvent_t start_ = nullptr, stop_ = nullptr;
+    bool active_ = false;
+};
+
+// Plan selection (host only).
+bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t n_waves_override,
+                      ScreenPlan* out);
+
+}  // namespace mips

@@ -1,0 +1,212 @@
+// Item preparation for the screen: per-item norms and screen copies, a
+// descending-norm item order, and the item tiles packed in matrix-core
+// operand order with per-tile bound maxima.
+//
+// Why a norm order: the paper's brute force scores items in storage order
+// (Section II-B).  Here the items are streamed in roughly descending ||i||
+// so that each user's K-th best score is found early; after that almost no
+// score of a 32 x 32 tile can reach it and the fused top-K stays on its fast
+// path.  The order changes speed only: the final order is decided by the
+// float64 keys and the original item index.
+#include "device_common.h"
+#include "internal.h"
+
+namespace mips {
+
+__global__ void zero_kernel(uint4* p, size_t n16) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    size_t n16 = (bytes + 15) / 16;   // regions are 256-byte aligned and padded
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    zero_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>((uint4*)p, n16);
+    return hipGetLastError();
+}
+
+// One thread per item: float64 norms of the row, its screen copy and the
+// residual, the descending-norm bucket, and the global maxima.
+template <int PREC>
+__global__ void item_stats_kernel(ItemPrepArgs a) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n_i) return;
+    const float* row = a.I + i * a.f;
+    double s2 = 0.0;
+    float amax = 0.0f;
+    bool finite = true;
+    for (int j = 0; j < a.f; ++j) {
+        float x = row[j];
+        finite = finite && __builtin_isfinite(x);
+        s2 += (double)x * (double)x;
+        amax = fmaxf(amax, fabsf(x));
+    }
+    int k = 0;
+    if (PREC == PREC_FP8) k = e4m3_row_scale_exp(amax);
+    double r2 = 0.0, q2 = 0.0;
+    if (PREC == PREC_FP32) {
+        float* q = (float*)a.qrow + i * a.f_pad;
+        for (int j = 0; j < a.f_pad; ++j) q[j] = (j < a.f) ? row[j] : 0.0f;
+        q2 = s2;
+    } else if (PREC == PREC_BF16) {
+        uint16_t* q = (uint16_t*)a.qrow + i * a.f_pad;
+        for (int j = 0; j < a.f_pad; ++j) {
+            float x = (j < a.f) ? row[j] : 0.0f;
+            uint16_t hb = f32_to_bf16_bits(x);
+            double d = (double)bf16_bits_to_f32(hb);
+            r2 += ((double)x - d) * ((double)x - d);
+            q2 += d * d;
+            q[j] = hb;
+        }
+    } else {
+        uint8_t* q = (uint8_t*)a.qrow + i * a.f_pad;
+        for (int j = 0; j < a.f_pad; ++j) {
+            float x = (j < a.f) ? row[j] : 0.0f;
+            uint32_t e = e4m3_encode(__builtin_ldexpf(x, -k));
+            double d = __builtin_ldexp((double)e4m3_decode(e), k);
+            r2 += ((double)x - d) * ((double)x - d);
+            q2 += d * d;
+            q[j] = (uint8_t)e;
+        }
+        a.kexp[i] = k;
+    }
+    if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
+    float C = norm_up_f32(sqrt(s2));
+    float E = norm_up_f32(sqrt(q2));
+    float G = (PREC == PREC_FP32) ? 0.0f
+                                  : norm_up_f32(sqrt(r2) + (double)a.gamma * sqrt(q2));
+    if (!finite) { C = 0.0f; E = 0.0f; G = 0.0f; }
+    a.Corig[i] = C;
+    a.Gorig[i] = G;
+    a.Eorig[i] = E;
+    atomicMax(&a.ctrl->cmax_bits, __float_as_uint(C));
+    atomicMax(&a.ctrl->emax_bits, __float_as_uint(E));
+    atomicMax(&a.ctrl->gmax_bits, __float_as_uint(G));
+    if (a.bucket) {
+        // descending ||i||: 16 buckets per octave from the float bits
+        int bk = (kBuckets - 1) - (int)(__float_as_uint(C) >> 19);
+        bk = bk < 0 ? 0 : (bk >= kBuckets ? kBuckets - 1 : bk);
+        a.bucket[i] = bk;
+        atomicAdd(&a.hist[bk], 1u);
+    }
+}
+
+// Exclusive scan of the bucket counts (one workgroup of 1024 threads).
+__global__ void __launch_bounds__(1024) bucket_scan_kernel(unsigned int* hist) {
+    __shared__ unsigned int part[1024];
+    int t = threadIdx.x;
+    unsigned int v[4];
+    unsigned int sum = 0;
+    for (int q = 0; q < 4; ++q) { v[q] = hist[t * 4 + q]; sum += v[q]; }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        unsigned int add = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    unsigned int run = part[t] - sum;   // exclusive prefix of this thread's group
+    for (int q = 0; q < 4; ++q) { hist[kBuckets + t * 4 + q] = run; run += v[q]; }
+}
+
+__global__ void bucket_scatter_kernel(ItemPrepArgs a) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n_i) return;
+    unsigned int pos = atomicAdd(&a.hist[kBuckets + a.bucket[i]], 1u);
+    a.perm[pos] = (int)i;
+}
+
+// One 64-thread workgroup per item tile: copy the 32 items' screen rows into
+// operand order (lane l = row l%32, half l/32 of the factors, chunk c) and
+// reduce the tile maxima of C and G.
+template <int PREC>
+__global__ void __launch_bounds__(64) item_pack_kernel(ItemPrepArgs a) {
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x, m = lane & 31, h = lane >> 5;
+    const int64_t p = b * kTile + m;
+    const int item = (p < a.n_i) ? a.perm[p] : -1;
+    const int half = a.f_pad / 2;
+    if (PREC == PREC_BF16) {
+        const uint4* src = (const uint4*)a.qrow;
+        uint4* dst = (uint4*)a.packed;
+        for (int c = 0; c < a.nch; ++c) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (item >= 0) v = src[((int64_t)item * a.f_pad + h * half + c * 8) / 8];
+            dst[(b * a.nch + c) * kWave + lane] = v;
+        }
+    } else if (PREC == PREC_FP8) {
+        const uint4* src = (const uint4*)a.qrow;
+        uint4* dst = (uint4*)a.packed;
+        for (int c = 0; c < a.nch; ++c) {
+            uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+            if (item >= 0) {
+                int64_t o = ((int64_t)item * a.f_pad + h * half + c * 32) / 16;
+                v0 = src[o];
+                v1 = src[o + 1];
+            }
+            int64_t d = ((b * a.nch + c) * kWave + lane) * 2;
+            dst[d] = v0;
+            dst[d + 1] = v1;
+        }
+        if (h == 0) a.pscale[p] = (item >= 0 ? a.kexp[item] : 0) + 127;
+    } else {
+        const float* src = (const float*)a.qrow;
+        float* dst = (float*)a.packed;
+        for (int c = 0; c < a.nch; ++c) {
+            float v = 0.0f;
+            if (item >= 0) v = src[(int64_t)item * a.f_pad + h * half + c];
+            dst[(b * a.nch + c) * kWave + lane] = v;
+        }
+    }
+    float cm = (item >= 0) ? a.Corig[item] : 0.0f;
+    float gm = (item >= 0) ? a.Gorig[item] : 0.0f;
+    for (int off = 16; off >= 1; off >>= 1) {
+        cm = fmaxf(cm, __shfl_xor(cm, off));
+        gm = fmaxf(gm, __shfl_xor(gm, off));
+    }
+    if (lane == 0) a.blockmax[b] = make_float2(cm, gm);
+}
+
+__global__ void nonfinite_scan_kernel(const float* U, int64_t nu, const float* I, int64_t ni,
+                                      Ctrl* ctrl) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t j = i; j < nu; j += stride) bad = bad || !__builtin_isfinite(U[j]);
+    for (int64_t j = i; j < ni; j += stride) bad = bad || !__builtin_isfinite(I[j]);
+    if (bad) atomicOr(&ctrl->nonfinite, 1u);
+}
+
+hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
+                                 int64_t ni_elems, Ctrl* ctrl, hipStream_t s) {
+    nonfinite_scan_kernel<<<dim3(1024), dim3(256), 0, s>>>(U, nu_elems, I, ni_elems, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s) {
+    const unsigned nb = (unsigned)((a.n_i + 255) / 256);
+    switch (prec) {
+        case PREC_FP32: item_stats_kernel<PREC_FP32><<<nb, 256, 0, s>>>(a); break;
+        case PREC_BF16: item_stats_kernel<PREC_BF16><<<nb, 256, 0, s>>>(a); break;
+        default: item_stats_kernel<PREC_FP8><<<nb, 256, 0, s>>>(a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !pack) return e;
+    bucket_scan_kernel<<<1, 1024, 0, s>>>(a.hist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bucket_scatter_kernel<<<nb, 256, 0, s>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned tiles = (unsigned)a.n_blk;
+    switch (prec) {
+        case PREC_FP32: item_pack_kernel<PREC_FP32><<<tiles, 64, 0, s>>>(a); break;
+        case PREC_BF16: item_pack_kernel<PREC_BF16><<<tiles, 64, 0, s>>>(a); break;
+        default: item_pack_kernel<PREC_FP8><<<tiles, 64, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mips

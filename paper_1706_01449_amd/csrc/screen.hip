@@ -1,0 +1,625 @@
+// Score tiles on the matrix cores fused with a per-user streaming top-K
+// (the brute force of paper Section II-B and the blocked walk of Maximus,
+// Section III-C/III-D), then certification with a float64 rescore, and the
+// exact float64 fallback.
+//
+// Tile layout.  One wave owns UB blocks of 32 users for the whole item sweep.
+// A 32x32 output tile has items as rows (operand A) and users as columns
+// (operand B), so lane l of the wave holds user l%32 and the 16 items
+// {8g + 4*(l/32) + q : g, q = 0..3} of the tile.  Both operands are indexed
+// the same way over the factors: lane half h = l/32 owns the contiguous
+// factor range [h*f_pad/2, (h+1)*f_pad/2), chunk c the next E of them.
+//
+// Streaming top-K.  Each lane keeps a register list of the KM largest lower
+// bounds it has seen (K real slots below KM-K +inf pads, so the last entry is
+// its K-th largest), and tau_u = max over the user's two lanes of that entry
+// is a valid lower bound on the user's K-th largest key.  Per tile a lane
+// takes the max of its 16 screened scores and compares it once with
+// tau_u - e_tile(u); only when some lane passes does the wave walk the 16
+// scores, insert their lower bounds and append (score, position) to the
+// user's candidate buffer.  The score matrix is never written out.
+//
+// Error bound of a screened score s (float32 accumulation of the screen
+// copies u', i'):
+//   |key(u,i) - s| <= A_u C_i + B_u G_i,
+//   A_u = ||u - u'|| + f 2^-52 ||u||,  B_u = ||u'||,
+//   C_i = ||i||,  G_i = ||i - i'|| + gamma ||i'||,
+// with gamma = n 2^-22 / (1 - n 2^-22) for the n products of a dot product
+// (4x the float32 unit roundoff, covering any summation order of the
+// accumulation); for the float32 screen A_u = (f 2^-52 + gamma) ||u||, B = 0.
+// A per-user slack (2^-20 of the largest magnitude involved) absorbs the
+// float32 rounding of every threshold and bound computed here.
+#include "device_common.h"
+#include "internal.h"
+
+namespace mips {
+
+// ---------------------------------------------------------------------------
+// Screen precisions: operand type and matrix-core instruction per chunk.
+// ---------------------------------------------------------------------------
+template <int PREC> struct Prec;
+
+template <> struct Prec<PREC_FP32> {
+    typedef float Op;
+    static constexpr int E = 1;                  // factors per lane per chunk
+    static constexpr int ESZ = 4;                // bytes per factor
+    __device__ static Op zero() { return 0.0f; }
+    __device__ static Op load_packed(const void* base, int64_t b, int c, int nch, int lane) {
+        return ((const float*)base)[(b * nch + c) * kWave + lane];
+    }
+    __device__ static Op load_row(const void* q, int64_t item, int f_pad, int off) {
+        return ((const float*)q)[item * f_pad + off];
+    }
+    __device__ static floatx16_t mma(Op a, Op b, floatx16_t acc, int, int) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+};
+
+template <> struct Prec<PREC_BF16> {
+    typedef bf16x8_t Op;
+    static constexpr int E = 8;
+    static constexpr int ESZ = 2;
+    __device__ static Op zero() { return __builtin_bit_cast(Op, intx4_t{0, 0, 0, 0}); }
+    __device__ static Op load_packed(const void* base, int64_t b, int c, int nch, int lane) {
+        return __builtin_bit_cast(Op, ((const intx4_t*)base)[(b * nch + c) * kWave + lane]);
+    }
+    __device__ static Op load_row(const void* q, int64_t item, int f_pad, int off) {
+        return __builtin_bit_cast(Op, ((const intx4_t*)q)[(item * f_pad + off) >> 3]);
+    }
+    __device__ static floatx16_t mma(Op a, Op b, floatx16_t acc, int, int) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+};
+
+template <> struct Prec<PREC_FP8> {
+    typedef intx8_t Op;
+    static constexpr int E = 32;
+    static constexpr int ESZ = 1;
+    __device__ static Op zero() { return intx8_t{0, 0, 0, 0, 0, 0, 0, 0}; }
+    __device__ static Op load_packed(const void* base, int64_t b, int c, int nch, int lane) {
+        return ((const intx8_t*)base)[(b * nch + c) * kWave + lane];
+    }
+    __device__ static Op load_row(const void* q, int64_t item, int f_pad, int off) {
+        return ((const intx8_t*)q)[(item * f_pad + off) >> 5];
+    }
+    // E8M0 scales: lane's row of A (item) and column of B (user).
+    __device__ static floatx16_t mma(Op a, Op b, floatx16_t acc, int sa, int sb) {
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
+    }
+};
+
+__device__ __forceinline__ double dot64(const float* __restrict__ u, const float* __restrict__ v,
+                                        int f) {
+    double acc = 0.0;
+    for (int j = 0; j < f; ++j) acc = __fma_rn((double)u[j], (double)v[j], acc);
+    return acc;
+}
+
+__device__ __forceinline__ void flag_user(const ScreenArgs& a, int64_t u) {
+    if (atomicCAS(&a.uflag[u], 0, 1) == 0) {
+        unsigned int k = atomicAdd(&a.ctrl->fb_count, 1u);
+        a.flist[k] = (int)u;
+    }
+}
+
+// Users of user block `ub` of wave `w`: brute force takes them in order, the
+// walk takes them from its tile (all users of a tile share one cluster).
+__device__ __forceinline__ int64_t user_of(const ScreenArgs& a, int UB, int64_t w, int ub, int n,
+                                           const int4& tile, bool* valid) {
+    if (a.walk) {
+        int r = ub * kTile + n;
+        *valid = r < tile.z;
+        return *valid ? (int64_t)a.sorted_users[tile.y + r] : 0;
+    }
+    int64_t u = (w * UB + ub) * kTile + n;
+    *valid = u < a.n_u;
+    return *valid ? u : 0;
+}
+
+// ---------------------------------------------------------------------------
+// The screen kernel.
+// ---------------------------------------------------------------------------
+template <int PREC, int KM, int NCH, int UB>
+__global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
+    typedef Prec<PREC> P;
+    typedef typename P::Op Op;
+    constexpr int E = P::E;
+    const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
+    const int64_t w = blockIdx.x;
+    const int nch = a.nch;
+    const int half = a.f_pad / 2;
+    const float ninf = -__builtin_inff(), pinf = __builtin_inff();
+
+    int4 tile = make_int4(0, 0, 0, 0);
+    if (a.walk) tile = a.tiles[w];
+    const int cluster = tile.x;
+
+    const float Cmax = __uint_as_float(a.ctrl->cmax_bits);
+    const float Emax = __uint_as_float(a.ctrl->emax_bits);
+    const float Gmax = __uint_as_float(a.ctrl->gmax_bits);
+
+    Op bu[UB][NCH];
+    float Au[UB], Bu[UB], slk[UB], tau[UB], Nup[UB];
+    float lst[UB][KM];
+    int cnt[UB], uscale[UB];
+    bool act[UB];
+    int64_t uid[UB];
+
+    // ---- prologue: load, quantise and measure this wave's users ----------
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub) {
+        bool valid;
+        const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
+        uid[ub] = u;
+        const float* urow = a.U + u * a.f;
+        double s2 = 0.0, r2 = 0.0, q2 = 0.0;
+        float amax = 0.0f;
+        bool finite = true;
+        if (valid) {
+            for (int j = h * half; j < h * half + half && j < a.f; ++j) {
+                float x = urow[j];
+                finite = finite && __builtin_isfinite(x);
+                s2 += (double)x * (double)x;
+                amax = fmaxf(amax, fabsf(x));
+            }
+        }
+        int k = 0;
+        if (PREC == PREC_FP8) {
+            amax = fmaxf(amax, xor32_f(amax));
+            k = e4m3_row_scale_exp(amax);
+        }
+        uscale[ub] = k + 127;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            Op op = P::zero();
+            if (c < nch && valid) {
+                const int j0 = h * half + c * E;
+                if constexpr (PREC == PREC_FP32) {
+                    float x = (j0 < a.f) ? urow[j0] : 0.0f;
+                    op = __builtin_bit_cast(Op, x);
+                } else if constexpr (PREC == PREC_BF16) {
+                    uint32_t wd[4];
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        float x0 = (j0 + e < a.f) ? urow[j0 + e] : 0.0f;
+                        float x1 = (j0 + e + 1 < a.f) ? urow[j0 + e + 1] : 0.0f;
+                        uint16_t b0 = f32_to_bf16_bits(x0), b1 = f32_to_bf16_bits(x1);
+                        double d0 = bf16_bits_to_f32(b0), d1 = bf16_bits_to_f32(b1);
+                        r2 += ((double)x0 - d0) * ((double)x0 - d0) + ((double)x1 - d1) * ((double)x1 - d1);
+                        q2 += d0 * d0 + d1 * d1;
+                        wd[e / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+                    }
+                    op = __builtin_bit_cast(Op, intx4_t{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]});
+                } else {
+                    uint32_t wd[8];
+#pragma unroll
+                    for (int e = 0; e < 32; e += 4) {
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            float x = (j0 + e + q < a.f) ? urow[j0 + e + q] : 0.0f;
+                            uint32_t byte = e4m3_encode(__builtin_ldexpf(x, -k));
+                            double d = __builtin_ldexp((double)e4m3_decode(byte), k);
+                            r2 += ((double)x - d) * ((double)x - d);
+                            q2 += d * d;
+                            word |= byte << (8 * q);
+                        }
+                        wd[e / 4] = word;
+                    }
+                    op = __builtin_bit_cast(Op, intx8_t{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3],
+                                                        (int)wd[4], (int)wd[5], (int)wd[6], (int)wd[7]});
+                }
+            }
+            bu[ub][c] = op;
+        }
+        s2 += xor32_d(s2);
+        r2 += xor32_d(r2);
+        q2 += xor32_d(q2);
+        finite = finite && (xor32_i((int)finite) != 0);
+        const double N64 = sqrt(s2);
+        float A, B;
+        if constexpr (PREC == PREC_FP32) {
+            A = norm_up_f32(((double)a.f * 0x1p-52 + (double)a.gamma) * N64);
+            B = 0.0f;
+        } else {
+            A = norm_up_f32(sqrt(r2) + (double)a.f * 0x1p-52 * N64);
+            B = norm_up_f32(sqrt(q2));
+        }
+        const double M = N64 * Cmax * 1.01 + (double)B * Emax * 1.01 + (double)A * Cmax +
+                         (double)B * Gmax;
+        Au[ub] = A;
+        Bu[ub] = B;
+        slk[ub] = round_up_f32(M * 0x1p-20 + 0x1p-100);
+        Nup[ub] = norm_up_f32(N64);
+        const bool degenerate = !finite || !(N64 > 0.0) || !(N64 * (double)Cmax < 0x1p100);
+        if (valid && degenerate && h == 0) {
+            if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
+            flag_user(a, u);
+        }
+        act[ub] = valid && !degenerate;
+        tau[ub] = ninf;
+        cnt[ub] = 0;
+#pragma unroll
+        for (int q = 0; q < KM; ++q) lst[ub][q] = (q < KM - a.K) ? pinf : ninf;
+    }
+
+    // ---- item sweep ------------------------------------------------------
+    const int64_t n_blk = a.n_blk;
+    int64_t b_done = n_blk;       // walk: number of tiles visited
+    const int* clist = a.walk ? a.lists + (int64_t)cluster * a.n_i : nullptr;
+    for (int64_t b = 0; b < n_blk; ++b) {
+        Op ai[NCH];
+        int iscale = 127;
+        if (!a.walk) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (c < nch) ai[c] = P::load_packed(a.packed, b, c, nch, lane);
+            if (PREC == PREC_FP8) iscale = a.pscale[b * kTile + n];
+        } else {
+            const int64_t p = b * kTile + n;
+            const int64_t item = (p < a.n_i) ? clist[p] : -1;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (c < nch) ai[c] = (item >= 0) ? P::load_row(a.qrow, item, a.f_pad, h * half + c * E)
+                                                 : P::zero();
+            if (PREC == PREC_FP8) iscale = (item >= 0) ? a.kexp[item] + 127 : 127;
+        }
+        const float2 bm = a.walk ? a.cblockmax[(int64_t)cluster * n_blk + b] : a.blockmax[b];
+        floatx16_t acc[UB];
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub) {
+            floatx16_t z = {};
+            acc[ub] = z;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (c < nch) acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
+        }
+        const bool last = (b + 1) * kTile > a.n_i;
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub) {
+            if (last) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t pos = b * kTile + 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (pos >= a.n_i) acc[ub][r] = __builtin_nanf("");  // never passes a compare
+                }
+            }
+            const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
+            const float thr = act[ub] ? tau[ub] - ee : pinf;
+            float m = acc[ub][0];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) m = fmaxf(m, acc[ub][r]);
+            if (ballot(m >= thr)) {
+                const int64_t ublk = w * UB + ub;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float v = acc[ub][r];
+                    const bool hit = v >= thr;
+                    if (ballot(hit)) {
+                        if (hit) {
+                            float x = v - ee;
+#pragma unroll
+                            for (int q = 0; q < KM; ++q) {
+                                const float hi = fmaxf(lst[ub][q], x);
+                                x = fminf(lst[ub][q], x);
+                                lst[ub][q] = hi;
+                            }
+                            const int pos = (int)(b * kTile) + 8 * (r >> 2) + 4 * h + (r & 3);
+                            if (cnt[ub] < a.cap)
+                                a.cand[((ublk * a.cap + cnt[ub]) << 6) + lane] =
+                                    make_int2(__float_as_int(v), pos);
+                            cnt[ub] += 1;
+                        }
+                    }
+                }
+                const float t = lst[ub][KM - 1];
+                tau[ub] = fmaxf(tau[ub], fmaxf(t, xor32_f(t)));
+            }
+        }
+        if (a.walk) {
+            // Stop test after this tile (Section III-C): every unvisited item i
+            // has key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is
+            // sorted, so the next entry's bound covers all of them.
+            const int64_t pnext = (b + 1) * kTile;
+            bool any = false;
+            if (b + 1 >= a.shared_blocks) {
+                const float bnext = (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
+#pragma unroll
+                for (int ub = 0; ub < UB; ++ub) {
+                    if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) act[ub] = false;
+                    any = any || act[ub];
+                }
+            } else {
+#pragma unroll
+                for (int ub = 0; ub < UB; ++ub) any = any || act[ub];
+            }
+            if (!ballot(any)) { b_done = b + 1; break; }
+        }
+    }
+
+    // ---- epilogue: hand the per-user state to certification --------------
+    unsigned long long visited = 0;
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub) {
+        const int64_t ublk = w * UB + ub;
+        a.cnt[(ublk << 6) + lane] = cnt[ub];
+        bool valid;
+        const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
+        if (valid && h == 0) {
+            a.uscal[u] = make_float4(Au[ub], Bu[ub], slk[ub], tau[ub]);
+            visited += (unsigned long long)(b_done * kTile < a.n_i ? b_done * kTile : a.n_i);
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) visited += __shfl_xor(visited, off);
+    if (lane == 0 && visited) atomicAdd(&a.ctrl->visited, visited);
+}
+
+// ---------------------------------------------------------------------------
+// Certification: keep the candidates whose upper bound reaches tau_u,
+// rescore them in float64 (left to right), and emit the first K by
+// (key desc, item index asc).  Same wave/user mapping as the screen.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
+    return ka > kb || (ka == kb && ia < ib);
+}
+
+template <int UB>
+__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a) {
+    extern __shared__ unsigned char smem[];
+    const int K = a.K;
+    double* skey = (double*)smem;                       // [64][K]
+    int* sidx = (int*)(smem + sizeof(double) * 64 * K); // [64][K]
+    __shared__ int scnt[64];
+    const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
+    const int64_t w = blockIdx.x;
+    int4 tile = make_int4(0, 0, 0, 0);
+    if (a.walk) tile = a.tiles[w];
+    const int* clist = a.walk ? a.lists + (int64_t)tile.x * a.n_i : nullptr;
+    double* mykey = skey + lane * K;
+    int* myidx = sidx + lane * K;
+
+    unsigned long long st_cand = 0, st_resc = 0, st_max = 0;
+    double st_abs = 0.0, st_rel = 0.0;
+    for (int ub = 0; ub < UB; ++ub) {
+        bool valid;
+        const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
+        const int64_t ublk = w * UB + ub;
+        const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
+        const bool flagged = valid ? (a.uflag[u] != 0) : true;
+        const float4 us = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        bool bad = c > a.cap;
+        int kept = 0;
+        if (!flagged) {
+            const float* urow = a.U + u * a.f;
+            const int cm = min(c, a.cap);
+            for (int s = 0; s < cm; ++s) {
+                const int2 e = a.cand[((ublk * a.cap + s) << 6) + lane];
+                const float sv = __int_as_float(e.x);
+                const int item = a.walk ? clist[e.y] : a.perm[e.y];
+                const float Ci = a.Corig[item];
+                const float eb = fmaf(us.x, Ci, fmaf(us.y, a.Gorig[item], us.z));
+                if (sv + eb >= us.w) {
+                    const double key = dot64(urow, a.I + (int64_t)item * a.f, a.f);
+                    const double err = fabs((double)sv - key);
+                    st_abs = fmax(st_abs, err);
+                    const double scale = (double)us.y > 0.0 ? (double)us.y * Ci : (double)us.x * Ci;
+                    if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+                    ++st_resc;
+                    // insert into this lane's sorted top-K list
+                    int len = kept < K ? kept : K;
+                    if (len == K && !before(key, item, mykey[K - 1], myidx[K - 1])) { ++kept; continue; }
+                    int pos = (len < K) ? len : K - 1;
+                    while (pos > 0 && before(key, item, mykey[pos - 1], myidx[pos - 1])) {
+                        mykey[pos] = mykey[pos - 1];
+                        myidx[pos] = myidx[pos - 1];
+                        --pos;
+                    }
+                    mykey[pos] = key;
+                    myidx[pos] = item;
+                    ++kept;
+                }
+            }
+            st_cand += (unsigned long long)c;
+        }
+        const int own = kept < K ? kept : K;
+        scnt[lane] = own;
+        __syncthreads();
+        const int other = scnt[lane ^ 32];
+        const int tot = kept + xor32_i(kept);
+        const bool anybad = bad || (xor32_i((int)bad) != 0);
+        const int ctot = c + xor32_i(c);
+        if (valid && h == 0) st_max = max(st_max, (unsigned long long)ctot);
+        if (valid && !flagged) {
+            if (anybad || tot < K) {
+                if (h == 0) flag_user(a, u);
+            } else {
+                const double* pk = skey + (lane ^ 32) * K;
+                const int* pi = sidx + (lane ^ 32) * K;
+                for (int x = 0; x < own; ++x) {
+                    const double kx = mykey[x];
+                    const int ix = myidx[x];
+                    int rank = x;   // own list is sorted
+                    for (int y = 0; y < other; ++y) rank += before(pk[y], pi[y], kx, ix) ? 1 : 0;
+                    if (rank < K) {
+                        a.out_idx[u * K + rank] = ix;
+                        a.out_score[u * K + rank] = kx;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // wave reductions of the statistics, one atomic each
+    for (int off = 32; off >= 1; off >>= 1) {
+        st_cand += __shfl_xor(st_cand, off);
+        st_resc += __shfl_xor(st_resc, off);
+        st_max = max(st_max, (unsigned long long)__shfl_xor(st_max, off));
+        st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
+        st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
+    }
+    if (lane == 0) {
+        if (st_cand) atomicAdd(&a.ctrl->cand_total, st_cand);
+        if (st_resc) atomicAdd(&a.ctrl->rescored, st_resc);
+        if (st_max) atomicMax(&a.ctrl->cand_max, st_max);
+        atomic_max_nonneg((double*)&a.ctrl->max_abs_err, st_abs);
+        atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact float64 fallback: all keys of a flagged user, radix selection of the
+// K-th (key desc, index asc), then ranks.  Used for users whose candidate
+// buffer overflowed, degenerate users (zero, non-finite, out of range) and
+// requests outside the screen's compiled shapes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ordered(double k) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(k);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
+    __shared__ unsigned int hist[256];
+    __shared__ double skey[kFallbackMaxK];
+    __shared__ int sidx[kFallbackMaxK];
+    __shared__ unsigned long long s_prefix;
+    __shared__ unsigned int s_need, s_sel, s_wave[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned int count = a.ctrl->fb_count;
+    double* keys = a.keys + (int64_t)blockIdx.x * a.n_i;
+    const int K = a.K;
+    for (unsigned int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int64_t u = a.flist[t];
+        const float* urow = a.U + u * a.f;
+        for (int64_t i = tid; i < a.n_i; i += 256) keys[i] = dot64(urow, a.I + i * a.f, a.f);
+        if (tid == 0) { s_prefix = 0ull; s_need = (unsigned)K; s_sel = 0u; }
+        __syncthreads();
+        unsigned long long mask = 0ull;
+        for (int pass = 7; pass >= 0; --pass) {
+            hist[tid] = 0u;
+            __syncthreads();
+            const unsigned long long prefix = s_prefix;
+            for (int64_t i = tid; i < a.n_i; i += 256) {
+                const unsigned long long m = ordered(keys[i]);
+                if ((m & mask) == prefix) atomicAdd(&hist[(m >> (8 * pass)) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned int need = s_need, cum = 0u;
+                int d = 255;
+                for (; d > 0; --d) {
+                    if (cum + hist[d] >= need) break;
+                    cum += hist[d];
+                }
+                s_need = need - cum;
+                s_prefix = prefix | ((unsigned long long)d << (8 * pass));
+            }
+            mask |= 255ull << (8 * pass);
+            __syncthreads();
+        }
+        const unsigned long long T = s_prefix;
+        const unsigned int take_eq = s_need;   // items equal to T to take, lowest indices first
+        unsigned int eq_before = 0u;
+        for (int64_t base = 0; base < a.n_i; base += 256) {
+            const int64_t i = base + tid;
+            unsigned long long m = 0ull;
+            double k = 0.0;
+            if (i < a.n_i) { k = keys[i]; m = ordered(k); }
+            const bool gt = i < a.n_i && m > T;
+            const bool eq = i < a.n_i && m == T;
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(eq);
+            const unsigned int below = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wave[wv] = __builtin_popcountll(bal);
+            __syncthreads();
+            unsigned int rank = eq_before + below;
+            for (int q = 0; q < wv; ++q) rank += s_wave[q];
+            const unsigned int chunk_eq = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+            if (gt || (eq && rank < take_eq)) {
+                const unsigned int slot = atomicAdd(&s_sel, 1u);
+                if (slot < (unsigned)kFallbackMaxK) { skey[slot] = k; sidx[slot] = (int)i; }
+            }
+            eq_before += chunk_eq;
+            __syncthreads();
+        }
+        const int sel = (int)min(s_sel, (unsigned)K);
+        for (int s = tid; s < sel; s += 256) {
+            const double kx = skey[s];
+            const int ix = sidx[s];
+            int rank = 0;
+            for (int y = 0; y < sel; ++y) rank += before(skey[y], sidx[y], kx, ix) ? 1 : 0;
+            if (rank < K) {
+                a.out_idx[u * K + rank] = ix;
+                a.out_score[u * K + rank] = kx;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void flag_all_kernel(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl) {
+    int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u < n_u) { uflag[u] = 1; flist[u] = (int)u; }
+    if (u == 0) ctrl->fb_count = (unsigned int)n_u;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <int PREC, int KM, int NCH, int UB>
+static hipError_t go_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
+    screen_kernel<PREC, KM, NCH, UB><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int PREC, int NCH>
+static hipError_t screen_km(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
+    switch (p.KM) {
+        case 1:  return go_screen<PREC, 1, NCH, ub_for(PREC, 1, NCH)>(p, a, s);
+        case 8:  return go_screen<PREC, 8, NCH, ub_for(PREC, 8, NCH)>(p, a, s);
+        case 16: return go_screen<PREC, 16, NCH, ub_for(PREC, 16, NCH)>(p, a, s);
+        case 32: return go_screen<PREC, 32, NCH, ub_for(PREC, 32, NCH)>(p, a, s);
+        default: return go_screen<PREC, 64, NCH, ub_for(PREC, 64, NCH)>(p, a, s);
+    }
+}
+
+hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
+    if (p.prec == PREC_BF16) {
+        switch (p.NCH) {
+            case 2: return screen_km<PREC_BF16, 2>(p, a, s);
+            case 4: return screen_km<PREC_BF16, 4>(p, a, s);
+            default: return screen_km<PREC_BF16, 8>(p, a, s);
+        }
+    } else if (p.prec == PREC_FP8) {
+        switch (p.NCH) {
+            case 1: return screen_km<PREC_FP8, 1>(p, a, s);
+            default: return screen_km<PREC_FP8, 2>(p, a, s);
+        }
+    }
+    switch (p.NCH) {
+        case 8: return screen_km<PREC_FP32, 8>(p, a, s);
+        case 32: return screen_km<PREC_FP32, 32>(p, a, s);
+        default: return screen_km<PREC_FP32, 64>(p, a, s);
+    }
+}
+
+hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
+    const size_t shm = (sizeof(double) + sizeof(int)) * 64 * (size_t)p.K;
+    const dim3 g((unsigned)p.n_waves), blk(64);
+    switch (p.UB) {
+        case 4: certify_kernel<4><<<g, blk, shm, s>>>(a); break;
+        case 2: certify_kernel<2><<<g, blk, shm, s>>>(a); break;
+        default: certify_kernel<1><<<g, blk, shm, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s) {
+    flag_all_kernel<<<dim3((unsigned)((n_u + 255) / 256)), dim3(256), 0, s>>>(n_u, uflag, flist, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s) {
+    fallback_kernel<<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace mips

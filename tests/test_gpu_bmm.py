@@ -1,0 +1,149 @@
+"""GPU parity of the brute-force path (score tiles + streaming top-K +
+certification + float64 rescore) against the CPU oracle, through the C ABI.
+
+Bar: indices bit-equal, scores (float64 keys) bit-equal, for every precision
+of the screen."""
+import numpy as np
+import pytest
+
+import mipsgen
+from gpu_util import assert_parity, gpu_topk, log
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp32", "bf16", "fp8"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("K", [1, 10])
+def test_tiny_workload_all_users(prec, K):
+    log(f"tiny workload prec={prec} K={K}")
+    U, I = mipsgen.generate("tiny", 0)
+    idx, score, st = gpu_topk(U, I, K, prec, stats=True)
+    assert_parity(idx, score, U, I, K)
+    assert st["nonfinite_input"] == 0
+    assert st["items_scored"] == U.shape[0] * I.shape[0]
+
+
+# (n_u, n_i, f, K): ragged tails in every dimension, f not a multiple of the
+# matrix-core K-step, K across the compiled list sizes.
+SHAPES = [
+    (1, 1, 1, 1), (3, 2, 5, 2), (33, 70, 17, 5), (100, 31, 3, 31), (70, 1000, 50, 64),
+    (65, 300, 128, 16), (40, 513, 100, 10), (257, 129, 64, 50), (129, 64, 16, 64),
+    (31, 95, 33, 8), (64, 1025, 7, 32),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_ragged_shapes(prec, shape):
+    n_u, n_i, f, K = shape
+    log(f"ragged {shape} prec={prec}")
+    U, I = mipsgen.generate("mf", 7, n_users=n_u, n_items=n_i, f=f)
+    idx, score = gpu_topk(U, I, K, prec)
+    assert_parity(idx, score, U, I, K)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+@pytest.mark.parametrize("shape", [(50, 300, 16, 65), (20, 300, 12, 300), (30, 400, 200, 10),
+                                   (10, 5000, 8, 1000)], ids=lambda s: "x".join(map(str, s)))
+def test_generic_exact_path(prec, shape):
+    # K > 64 or f > 128 runs on the exact float64 kernel for every user
+    n_u, n_i, f, K = shape
+    log(f"generic {shape} prec={prec}")
+    U, I = mipsgen.generate("tiny", 3, n_users=n_u, n_items=n_i, f=f)
+    idx, score, st = gpu_topk(U, I, K, prec, stats=True)
+    assert_parity(idx, score, U, I, K)
+    assert st["overflow_users"] == n_u
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ties_zero_rows_duplicates(prec):
+    log(f"ties prec={prec}")
+    U, I = mipsgen.generate("mf", 11, n_users=150, n_items=900, f=24)
+    U[0] = 0.0                   # zero user: all keys 0 -> items 0..K-1
+    U[77] = 0.0
+    I[5] = I[100]                # exact duplicates tie; lower index first
+    I[6] = I[100]
+    I[899] = I[100]
+    I[300] = 0.0                 # zero item
+    U[10] = -U[11]
+    idx, score = gpu_topk(U, I, 20, prec)
+    assert_parity(idx, score, U, I, 20)
+    np.testing.assert_array_equal(idx[0], np.arange(20))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_integer_massive_ties(prec):
+    # f = 1 with small integers: thousands of exact ties per user
+    log(f"massive ties prec={prec}")
+    rng = np.random.default_rng(3)
+    U = rng.integers(-3, 4, size=(90, 1)).astype(np.float32)
+    I = rng.integers(-5, 6, size=(2000, 1)).astype(np.float32)
+    idx, score, st = gpu_topk(U, I, 16, prec, stats=True)
+    assert_parity(idx, score, U, I, 16)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_identity_items_closed_form(prec):
+    f = 40
+    I = np.eye(f, dtype=np.float32)
+    rng = np.random.default_rng(9)
+    U = rng.standard_normal((70, f)).astype(np.float32)
+    idx, score = gpu_topk(U, I, f, prec)
+    cols = np.arange(f)
+    for u in range(70):
+        np.testing.assert_array_equal(idx[u], np.lexsort((cols, -U[u])))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_wide_dynamic_range(prec):
+    log(f"dynamic range prec={prec}")
+    U, I = mipsgen.generate("mf", 5, n_users=200, n_items=1500, f=32)
+    I[:500] *= 1e-6
+    I[500:510] *= 1e3
+    U[:50] *= 1e-8
+    U[50:60] *= 1e8
+    idx, score = gpu_topk(U, I, 10, prec)
+    assert_parity(idx, score, U, I, 10)
+
+
+def test_nonfinite_input_reported():
+    import paper_1706_01449_amd as mips
+    U, I = mipsgen.generate("tiny", 0, n_users=64, n_items=128)
+    I[3, 2] = np.nan
+    with pytest.raises(mips.MipsError) as ei:
+        gpu_topk(U, I, 5, "bf16", stats=True)
+    assert ei.value.code == -2
+
+
+def test_deterministic_repeat():
+    U, I = mipsgen.generate("mf", 2, n_users=3000, n_items=4000, f=50)
+    a = gpu_topk(U, I, 10, "bf16")
+    b = gpu_topk(U, I, 10, "bf16")
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("K", [1, 5, 10, 50])
+def test_mf_full_size_sampled(prec, K):
+    """480,000 x 17,770, f = 50 (the Netflix shape): every user computed on the
+    GPU in the benchmark's configuration, 1,500 sampled users checked."""
+    log(f"mf full size prec={prec} K={K}")
+    U, I = _mf_full()
+    idx, score, st = gpu_topk(U, I, K, prec, stats=True)
+    users = mipsgen.sample_users(U.shape[0], 1500, seed=K)
+    assert_parity(idx, score, U, I, K, users=users)
+    log(f"  stats {st}")
+    assert st["overflow_users"] <= U.shape[0] // 1000
+    # every returned row is sorted by (key desc, index asc) and duplicate-free
+    assert np.all(np.diff(score, axis=1) <= 0)
+
+
+_MF = {}
+
+
+def _mf_full():
+    if "x" not in _MF:
+        _MF["x"] = mipsgen.generate("mf", 0)
+    return _MF["x"]
