@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -97,10 +98,19 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
     }
     p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64)));
     p.UB = ub_for(prec, p.KM, p.NCH);
+    // Candidate slots per lane (half a user's items): room for the K-list
+    // entries plus the items that pass before the threshold settles; the
+    // coarser E4M3 screen keeps several times more.
     if (prec == PREC_FP8)
-        p.cap = std::max(256, 4 * p.KM + 64);
+        p.cap = std::max(256, 8 * p.KM + 64);
     else
         p.cap = std::max(64, 2 * p.KM + 32);
+    // Test-only override of the candidate slots per lane (forces the overflow
+    // fallback when small); read from the environment at every call.
+    if (const char* env = std::getenv("MIPS_DEBUG_CAND_CAP")) {
+        int v = std::atoi(env);
+        if (v >= 1) p.cap = v;
+    }
     p.kc = p.cap;
     p.n_blk = (n_i + 31) / 32;
     p.n_i_pad = p.n_blk * 32;

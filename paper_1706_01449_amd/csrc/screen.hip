@@ -116,6 +116,15 @@ __device__ __forceinline__ int64_t user_of(const ScreenArgs& a, int UB, int64_t 
     return *valid ? u : 0;
 }
 
+// Entry `idx` (wave-uniform, known only at run time) of a register list.
+template <int KM>
+__device__ __forceinline__ float pick(const float (&l)[KM], int idx) {
+    float v = l[0];
+#pragma unroll
+    for (int q = 1; q < KM; ++q) v = (q == idx) ? l[q] : v;
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // The screen kernel.
 // ---------------------------------------------------------------------------
@@ -215,7 +224,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         s2 += xor32_d(s2);
         r2 += xor32_d(r2);
         q2 += xor32_d(q2);
-        finite = finite && (xor32_i((int)finite) != 0);
+        // every lane must take part in the exchange (no short-circuit)
+        const int finite_p = xor32_i((int)finite);
+        finite = finite && (finite_p != 0);
         const double N64 = sqrt(s2);
         float A, B;
         if constexpr (PREC == PREC_FP32) {
@@ -242,6 +253,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
         for (int q = 0; q < KM; ++q) lst[ub][q] = (q < KM - a.K) ? pinf : ninf;
     }
+
+    // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
+    const int hidx = KM - (a.K / 2) - 1;
 
     // ---- item sweep ------------------------------------------------------
     const int64_t n_blk = a.n_blk;
@@ -312,8 +326,13 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         }
                     }
                 }
+                // Valid lower bounds on the user's K-th largest key: each
+                // lane's own K-th largest, and min over the two lanes of their
+                // ceil(K/2)-th largest (together at least K values reach it).
                 const float t = lst[ub][KM - 1];
-                tau[ub] = fmaxf(tau[ub], fmaxf(t, xor32_f(t)));
+                const float th = pick(lst[ub], hidx);
+                const float tp = xor32_f(t), thp = xor32_f(th);
+                tau[ub] = fmaxf(tau[ub], fmaxf(fmaxf(t, tp), fminf(th, thp)));
             }
         }
         if (a.walk) {
@@ -426,7 +445,8 @@ __global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a) {
         __syncthreads();
         const int other = scnt[lane ^ 32];
         const int tot = kept + xor32_i(kept);
-        const bool anybad = bad || (xor32_i((int)bad) != 0);
+        const int bad_p = xor32_i((int)bad);   // all lanes exchange
+        const bool anybad = bad || (bad_p != 0);
         const int ctot = c + xor32_i(c);
         if (valid && h == 0) st_max = max(st_max, (unsigned long long)ctot);
         if (valid && !flagged) {

@@ -147,3 +147,15 @@ def _mf_full():
     if "x" not in _MF:
         _MF["x"] = mipsgen.generate("mf", 0)
     return _MF["x"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_forced_candidate_overflow_stays_exact(prec, monkeypatch):
+    """A test-only cap of 2 candidate slots per lane forces most users onto the
+    exact float64 fallback; the answer must not change."""
+    U, I = mipsgen.generate("mf", 4, n_users=700, n_items=3000, f=50)
+    monkeypatch.setenv("MIPS_DEBUG_CAND_CAP", "2")
+    idx, score, st = gpu_topk(U, I, 10, prec, stats=True)
+    monkeypatch.delenv("MIPS_DEBUG_CAND_CAP")
+    assert st["overflow_users"] > 600
+    assert_parity(idx, score, U, I, 10)
