@@ -163,10 +163,10 @@ int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, in
  * indices fixed, S[u,k] = U[u] . I[idx[u,k]] and G = dL/dS:
  *   dU[u]  = sum_k G[u,k] I[idx[u,k]]                      (gather)
  *   dI[i]  = sum over (u,k) with idx[u,k] = i of G[u,k] U[u]  (scatter-add)
- * dU (n_u x f) and dI (n_i x f) are overwritten.  dU is deterministic; dI is
- * accumulated with float32 atomics, so its last bits may vary run to run.
- * idx entries must lie in [0, n_i) (checked on the device; a bad index makes
- * the call's stats-free return value MIPS_OK but is skipped and counted).
+ * dU (n_u x f) and dI (n_i x f) are overwritten.  dU is summed in k order
+ * and is deterministic; dI is accumulated with float32 atomics, so its last
+ * bits may vary run to run.  idx entries outside [0, n_i) are skipped.
+ * Limits: 1 <= n_u, n_i < 2^31; 1 <= f <= 4096; K >= 1.
  * ------------------------------------------------------------------------- */
 int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
                        int32_t K, const int32_t* idx, const float* grad_scores, float* dU,

@@ -96,7 +96,7 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
         p.nch = p.f_pad / 64;
         p.NCH = p.nch <= 1 ? 1 : 2;
     }
-    p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64)));
+    p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 10 ? 10 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64))));
     p.UB = ub_for(prec, p.KM, p.NCH);
     // Candidate slots per lane (half a user's items): room for the K-list
     // entries plus the items that pass before the threshold settles; the
@@ -249,6 +249,21 @@ int mips_profile_read(double* ms, int64_t* launches) {
     return rc;
 }
 
+int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
+                       int32_t K, const int32_t* idx, const float* grad_scores, float* dU,
+                       float* dI, void* stream) {
+    if (n_u < 1 || n_i < 1 || n_i >= ((int64_t)1 << 31) || n_u >= ((int64_t)1 << 31))
+        return fail(MIPS_ERR_ARG, "n_u, n_i must be in [1, 2^31)");
+    if (f < 1 || f > 4096) return fail(MIPS_ERR_ARG, "f must be in [1, 4096] (got %d)", f);
+    if (K < 1) return fail(MIPS_ERR_ARG, "K must be >= 1 (got %d)", K);
+    if (!U || !I || !idx || !grad_scores || !dU || !dI) return fail(MIPS_ERR_ARG, "null array pointer");
+    hipStream_t s = (hipStream_t)stream;
+    PhaseTimer t(MIPS_PHASE_BACKWARD, s);
+    hipError_t e = launch_backward(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI, s);
+    if (e != hipSuccess) return hip_fail(e, "backward");
+    return MIPS_OK;
+}
+
 size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t K,
                                     int32_t precision) {
     if (check_common(n_u, n_i, f, K, precision) != MIPS_OK) return 0;
@@ -392,9 +407,4 @@ int mips_maximus_export(const mips_maximus_index*, int32_t*, int32_t*, int64_t*,
                         double*, int32_t*, int32_t*, float*, void*) {
     return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
 }
-int mips_topk_backward(const float*, const float*, int64_t, int64_t, int32_t, int32_t,
-                       const int32_t*, const float*, float*, float*, void*) {
-    return fail(MIPS_ERR_UNSUPPORTED, "backward is not built yet");
-}
-
 }  // extern "C"

@@ -11,12 +11,15 @@ namespace mips {
 // Precision codes (same values as the public mips_precision enum).
 enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
 
-// User blocks of 32 per screen wave: fewer when the register K-list (KM
-// entries per user block) or the float32 operands (NCH registers per user
-// block) grow.
+// User blocks of 32 per screen wave.  Each user block holds its operand
+// registers, two accumulator sets (software pipeline) and a KM-entry K-list,
+// so fewer blocks fit when the list or the operands grow.
 __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap) {
-    return prec == PREC_FP32 ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
-                             : (km <= 16 ? 4 : (km == 32 ? 2 : 1));
+    return prec == PREC_FP32
+               ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
+               : ((prec == PREC_BF16 && nch_cap >= 8)
+                      ? (km <= 16 ? 2 : 1)
+                      : (km <= 10 ? 4 : (km <= 16 ? 3 : (km <= 32 ? 2 : 1))));
 }
 
 // Device-resident control block of one call.  Zeroed at the start of every
@@ -133,6 +136,8 @@ hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t 
 hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s);
 
+hipError_t launch_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int f, int K,
+                           const int32_t* idx, const float* G, float* dU, float* dI, hipStream_t s);
 hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
                                  int64_t ni_elems, Ctrl* ctrl, hipStream_t s);
 

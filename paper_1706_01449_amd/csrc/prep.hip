@@ -19,12 +19,23 @@ __global__ void zero_kernel(uint4* p, size_t n16) {
     for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
 }
 
+__global__ void zero_tail_kernel(unsigned char* p, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Zero `bytes` bytes at p (p 16-byte aligned): whole 16-byte words first,
+// then the tail byte by byte, so nothing past p + bytes is touched.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
-    size_t n16 = (bytes + 15) / 16;   // regions are 256-byte aligned and padded
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    zero_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>((uint4*)p, n16);
+    const size_t n16 = bytes / 16;
+    if (n16) {
+        size_t blocks = (n16 + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        zero_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>((uint4*)p, n16);
+    }
+    const size_t tail = bytes - n16 * 16;
+    if (tail) zero_tail_kernel<<<dim3(1), dim3(16), 0, s>>>((unsigned char*)p + n16 * 16, tail);
     return hipGetLastError();
 }
 

@@ -116,12 +116,15 @@ __device__ __forceinline__ int64_t user_of(const ScreenArgs& a, int UB, int64_t 
     return *valid ? u : 0;
 }
 
-// Entry `idx` (wave-uniform, known only at run time) of a register list.
+// Entry `idx` (wave-uniform, known only at run time) of a register list
+// sorted in descending order: the max over the entries from idx on.  Written
+// as a masked reduction so that the list stays in registers (a select chain
+// would be turned into an indexed load from scratch memory).
 template <int KM>
-__device__ __forceinline__ float pick(const float (&l)[KM], int idx) {
-    float v = l[0];
+__device__ __forceinline__ float pick_sorted(const float (&l)[KM], int idx) {
+    float v = -__builtin_inff();
 #pragma unroll
-    for (int q = 1; q < KM; ++q) v = (q == idx) ? l[q] : v;
+    for (int q = 0; q < KM; ++q) v = fmaxf(v, (q >= idx) ? l[q] : -__builtin_inff());
     return v;
 }
 
@@ -258,28 +261,34 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     const int hidx = KM - (a.K / 2) - 1;
 
     // ---- item sweep ------------------------------------------------------
+    // Two-stage software pipeline: while the VALU runs the top-K epilogue of
+    // tile b, the matrix cores already work on tile b+1 (second accumulator
+    // set) and the operands of tile b+2 are in flight.
     const int64_t n_blk = a.n_blk;
-    int64_t b_done = n_blk;       // walk: number of tiles visited
+    int64_t b_done = n_blk;       // tiles visited (the walk may stop early)
     const int* clist = a.walk ? a.lists + (int64_t)cluster * a.n_i : nullptr;
-    for (int64_t b = 0; b < n_blk; ++b) {
-        Op ai[NCH];
-        int iscale = 127;
+
+    // This lane's A-operand chunks of tile b (row n), the row's item index
+    // (-1 past the end) and, for E4M3, the row's E8M0 scale byte.
+    auto load_tile = [&](int64_t b, Op (&ai)[NCH], int& item, int& iscale) __attribute__((always_inline)) {
+        const int64_t p = b * kTile + n;
         if (!a.walk) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
                 if (c < nch) ai[c] = P::load_packed(a.packed, b, c, nch, lane);
-            if (PREC == PREC_FP8) iscale = a.pscale[b * kTile + n];
+            item = (p < a.n_i) ? a.perm[p] : -1;
+            if (PREC == PREC_FP8) iscale = a.pscale[p];
         } else {
-            const int64_t p = b * kTile + n;
-            const int64_t item = (p < a.n_i) ? clist[p] : -1;
+            item = (p < a.n_i) ? clist[p] : -1;
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
                 if (c < nch) ai[c] = (item >= 0) ? P::load_row(a.qrow, item, a.f_pad, h * half + c * E)
                                                  : P::zero();
             if (PREC == PREC_FP8) iscale = (item >= 0) ? a.kexp[item] + 127 : 127;
         }
-        const float2 bm = a.walk ? a.cblockmax[(int64_t)cluster * n_blk + b] : a.blockmax[b];
-        floatx16_t acc[UB];
+    };
+
+    auto mma_tile = [&](const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB]) __attribute__((always_inline)) {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
             floatx16_t z = {};
@@ -288,6 +297,12 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             for (int c = 0; c < NCH; ++c)
                 if (c < nch) acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
         }
+    };
+
+    // Streaming top-K over tile b; returns false once every user of a walk
+    // wave has stopped.
+    auto epi_tile = [&](int64_t b, floatx16_t (&acc)[UB], int item) __attribute__((always_inline)) -> bool {
+        const float2 bm = a.walk ? a.cblockmax[(int64_t)cluster * n_blk + b] : a.blockmax[b];
         const bool last = (b + 1) * kTile > a.n_i;
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
@@ -310,6 +325,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     const float v = acc[ub][r];
                     const bool hit = v >= thr;
                     if (ballot(hit)) {
+                        // item index of output row 8g + 4h + q, held by lane (row)
+                        const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                        const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
                         if (hit) {
                             float x = v - ee;
 #pragma unroll
@@ -318,10 +336,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                                 x = fminf(lst[ub][q], x);
                                 lst[ub][q] = hi;
                             }
-                            const int pos = (int)(b * kTile) + 8 * (r >> 2) + 4 * h + (r & 3);
                             if (cnt[ub] < a.cap)
                                 a.cand[((ublk * a.cap + cnt[ub]) << 6) + lane] =
-                                    make_int2(__float_as_int(v), pos);
+                                    make_int2(__float_as_int(v), orig);
                             cnt[ub] += 1;
                         }
                     }
@@ -330,30 +347,52 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 // lane's own K-th largest, and min over the two lanes of their
                 // ceil(K/2)-th largest (together at least K values reach it).
                 const float t = lst[ub][KM - 1];
-                const float th = pick(lst[ub], hidx);
+                const float th = pick_sorted(lst[ub], hidx);
                 const float tp = xor32_f(t), thp = xor32_f(th);
                 tau[ub] = fmaxf(tau[ub], fmaxf(fmaxf(t, tp), fminf(th, thp)));
             }
         }
-        if (a.walk) {
-            // Stop test after this tile (Section III-C): every unvisited item i
-            // has key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is
-            // sorted, so the next entry's bound covers all of them.
-            const int64_t pnext = (b + 1) * kTile;
-            bool any = false;
-            if (b + 1 >= a.shared_blocks) {
-                const float bnext = (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
+        if (!a.walk) return true;
+        // Stop test after this tile (Section III-C): every unvisited item i has
+        // key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is sorted,
+        // so the next entry's bound covers all of them.
+        const int64_t pnext = (b + 1) * kTile;
+        bool any = false;
+        if (b + 1 >= a.shared_blocks) {
+            const float bnext =
+                (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
 #pragma unroll
-                for (int ub = 0; ub < UB; ++ub) {
-                    if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) act[ub] = false;
-                    any = any || act[ub];
-                }
-            } else {
-#pragma unroll
-                for (int ub = 0; ub < UB; ++ub) any = any || act[ub];
+            for (int ub = 0; ub < UB; ++ub) {
+                if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) act[ub] = false;
+                any = any || act[ub];
             }
-            if (!ballot(any)) { b_done = b + 1; break; }
+        } else {
+#pragma unroll
+            for (int ub = 0; ub < UB; ++ub) any = any || act[ub];
         }
+        return ballot(any) != 0;
+    };
+
+    Op oA[NCH], oB[NCH];
+    int itA = -1, itB = -1, scA = 127, scB = 127;
+    floatx16_t accA[UB], accB[UB];
+    if (n_blk > 0) {
+        load_tile(0, oA, itA, scA);
+        mma_tile(oA, scA, accA);
+    }
+    if (n_blk > 1) load_tile(1, oB, itB, scB);
+    for (int64_t b = 0; b < n_blk; b += 2) {
+        // accA: tile b issued; oB: operands of tile b+1 in flight
+        const int eA = itA;
+        if (b + 1 < n_blk) mma_tile(oB, scB, accB);
+        if (b + 2 < n_blk) load_tile(b + 2, oA, itA, scA);
+        if (!epi_tile(b, accA, eA)) { b_done = b + 1; break; }
+        if (b + 1 >= n_blk) break;
+        // accB: tile b+1 issued; oA: operands of tile b+2 in flight
+        const int eB = itB;
+        if (b + 2 < n_blk) mma_tile(oA, scA, accA);
+        if (b + 3 < n_blk) load_tile(b + 3, oB, itB, scB);
+        if (!epi_tile(b + 1, accB, eB)) { b_done = b + 2; break; }
     }
 
     // ---- epilogue: hand the per-user state to certification --------------
@@ -382,94 +421,122 @@ __device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
     return ka > kb || (ka == kb && ia < ib);
 }
 
-template <int UB>
-__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a) {
+// float64 key of (u, i): left-to-right sum over the factors, read two floats
+// at a time when both rows are 8-byte aligned (f even).
+__device__ __forceinline__ double dot64_rows(const float* __restrict__ u,
+                                             const float* __restrict__ v, int f) {
+    double acc = 0.0;
+    if ((f & 1) == 0) {
+        const float2* u2 = (const float2*)u;
+        const float2* v2 = (const float2*)v;
+        for (int j = 0; j < (f >> 1); ++j) {
+            const float2 x = u2[j], y = v2[j];
+            acc = __fma_rn((double)x.x, (double)y.x, acc);
+            acc = __fma_rn((double)x.y, (double)y.y, acc);
+        }
+        return acc;
+    }
+    return dot64(u, v, f);
+}
+
+// One wave per block of 32 users (same lane mapping as the screen: lane l
+// holds half l/32 of user l%32's candidates).
+__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a, int UB) {
     extern __shared__ unsigned char smem[];
     const int K = a.K;
     double* skey = (double*)smem;                       // [64][K]
     int* sidx = (int*)(smem + sizeof(double) * 64 * K); // [64][K]
     __shared__ int scnt[64];
     const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
-    const int64_t w = blockIdx.x;
+    const int64_t ublk = blockIdx.x;
+    const int64_t w = ublk / UB;
+    const int ub = (int)(ublk - w * UB);
     int4 tile = make_int4(0, 0, 0, 0);
     if (a.walk) tile = a.tiles[w];
-    const int* clist = a.walk ? a.lists + (int64_t)tile.x * a.n_i : nullptr;
     double* mykey = skey + lane * K;
     int* myidx = sidx + lane * K;
 
-    unsigned long long st_cand = 0, st_resc = 0, st_max = 0;
+    bool valid;
+    const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
+    const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
+    const bool flagged = valid ? (a.uflag[u] != 0) : true;
+    const float4 us = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool bad = c > a.cap;
+    int kept = 0;
+    unsigned long long st_resc = 0;
     double st_abs = 0.0, st_rel = 0.0;
-    for (int ub = 0; ub < UB; ++ub) {
-        bool valid;
-        const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
-        const int64_t ublk = w * UB + ub;
-        const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
-        const bool flagged = valid ? (a.uflag[u] != 0) : true;
-        const float4 us = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-        bool bad = c > a.cap;
-        int kept = 0;
-        if (!flagged) {
-            const float* urow = a.U + u * a.f;
-            const int cm = min(c, a.cap);
-            for (int s = 0; s < cm; ++s) {
-                const int2 e = a.cand[((ublk * a.cap + s) << 6) + lane];
-                const float sv = __int_as_float(e.x);
-                const int item = a.walk ? clist[e.y] : a.perm[e.y];
-                const float Ci = a.Corig[item];
-                const float eb = fmaf(us.x, Ci, fmaf(us.y, a.Gorig[item], us.z));
-                if (sv + eb >= us.w) {
-                    const double key = dot64(urow, a.I + (int64_t)item * a.f, a.f);
-                    const double err = fabs((double)sv - key);
-                    st_abs = fmax(st_abs, err);
-                    const double scale = (double)us.y > 0.0 ? (double)us.y * Ci : (double)us.x * Ci;
-                    if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
-                    ++st_resc;
-                    // insert into this lane's sorted top-K list
-                    int len = kept < K ? kept : K;
-                    if (len == K && !before(key, item, mykey[K - 1], myidx[K - 1])) { ++kept; continue; }
-                    int pos = (len < K) ? len : K - 1;
-                    while (pos > 0 && before(key, item, mykey[pos - 1], myidx[pos - 1])) {
-                        mykey[pos] = mykey[pos - 1];
-                        myidx[pos] = myidx[pos - 1];
-                        --pos;
-                    }
-                    mykey[pos] = key;
-                    myidx[pos] = item;
-                    ++kept;
-                }
+    if (!flagged) {
+        const float* urow = a.U + u * a.f;
+        const int cm = min(c, a.cap);
+        const int2* cbase = a.cand + ((ublk * a.cap) << 6) + lane;
+        constexpr int CH = 4;     // candidates fetched together
+        for (int s0 = 0; s0 < cm; s0 += CH) {
+            int2 e[CH];
+            float Ci[CH], Gi[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) e[q] = (s0 + q < cm) ? cbase[(int64_t)(s0 + q) << 6] : make_int2(0, -1);
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                Ci[q] = (e[q].y >= 0) ? a.Corig[e[q].y] : 0.0f;
+                Gi[q] = (e[q].y >= 0) ? a.Gorig[e[q].y] : 0.0f;
             }
-            st_cand += (unsigned long long)c;
-        }
-        const int own = kept < K ? kept : K;
-        scnt[lane] = own;
-        __syncthreads();
-        const int other = scnt[lane ^ 32];
-        const int tot = kept + xor32_i(kept);
-        const int bad_p = xor32_i((int)bad);   // all lanes exchange
-        const bool anybad = bad || (bad_p != 0);
-        const int ctot = c + xor32_i(c);
-        if (valid && h == 0) st_max = max(st_max, (unsigned long long)ctot);
-        if (valid && !flagged) {
-            if (anybad || tot < K) {
-                if (h == 0) flag_user(a, u);
-            } else {
-                const double* pk = skey + (lane ^ 32) * K;
-                const int* pi = sidx + (lane ^ 32) * K;
-                for (int x = 0; x < own; ++x) {
-                    const double kx = mykey[x];
-                    const int ix = myidx[x];
-                    int rank = x;   // own list is sorted
-                    for (int y = 0; y < other; ++y) rank += before(pk[y], pi[y], kx, ix) ? 1 : 0;
-                    if (rank < K) {
-                        a.out_idx[u * K + rank] = ix;
-                        a.out_score[u * K + rank] = kx;
-                    }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int item = e[q].y;
+                if (item < 0) continue;
+                const float sv = __int_as_float(e[q].x);
+                const float eb = fmaf(us.x, Ci[q], fmaf(us.y, Gi[q], us.z));
+                if (!(sv + eb >= us.w)) continue;
+                const double key = dot64_rows(urow, a.I + (int64_t)item * a.f, a.f);
+                const double err = fabs((double)sv - key);
+                st_abs = fmax(st_abs, err);
+                const double scale = (us.y > 0.0f ? (double)us.y : (double)us.x) * (double)Ci[q];
+                if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+                ++st_resc;
+                // insert into this lane's sorted top-K list
+                const int len = kept < K ? kept : K;
+                ++kept;
+                if (len == K && !before(key, item, mykey[K - 1], myidx[K - 1])) continue;
+                int pos = (len < K) ? len : K - 1;
+                while (pos > 0 && before(key, item, mykey[pos - 1], myidx[pos - 1])) {
+                    mykey[pos] = mykey[pos - 1];
+                    myidx[pos] = myidx[pos - 1];
+                    --pos;
                 }
+                mykey[pos] = key;
+                myidx[pos] = item;
             }
         }
-        __syncthreads();
+    }
+    const int own = kept < K ? kept : K;
+    scnt[lane] = own;
+    __syncthreads();
+    const int other = scnt[lane ^ 32];
+    const int tot = kept + xor32_i(kept);
+    const int bad_p = xor32_i((int)bad);   // all lanes exchange
+    const bool anybad = bad || (bad_p != 0);
+    const int ctot = c + xor32_i(c);
+    if (valid && !flagged) {
+        if (anybad || tot < K) {
+            if (h == 0) flag_user(a, u);
+        } else {
+            const double* pk = skey + (lane ^ 32) * K;
+            const int* pi = sidx + (lane ^ 32) * K;
+            for (int x = 0; x < own; ++x) {
+                const double kx = mykey[x];
+                const int ix = myidx[x];
+                int rank = x;   // own list is sorted
+                for (int y = 0; y < other; ++y) rank += before(pk[y], pi[y], kx, ix) ? 1 : 0;
+                if (rank < K) {
+                    a.out_idx[u * K + rank] = ix;
+                    a.out_score[u * K + rank] = kx;
+                }
+            }
+        }
     }
     // wave reductions of the statistics, one atomic each
+    unsigned long long st_cand = (!flagged) ? (unsigned long long)c : 0ull;
+    unsigned long long st_max = (valid && h == 0) ? (unsigned long long)ctot : 0ull;
     for (int off = 32; off >= 1; off >>= 1) {
         st_cand += __shfl_xor(st_cand, off);
         st_resc += __shfl_xor(st_resc, off);
@@ -595,6 +662,7 @@ static hipError_t screen_km(const ScreenPlan& p, const ScreenArgs& a, hipStream_
     switch (p.KM) {
         case 1:  return go_screen<PREC, 1, NCH, ub_for(PREC, 1, NCH)>(p, a, s);
         case 8:  return go_screen<PREC, 8, NCH, ub_for(PREC, 8, NCH)>(p, a, s);
+        case 10: return go_screen<PREC, 10, NCH, ub_for(PREC, 10, NCH)>(p, a, s);
         case 16: return go_screen<PREC, 16, NCH, ub_for(PREC, 16, NCH)>(p, a, s);
         case 32: return go_screen<PREC, 32, NCH, ub_for(PREC, 32, NCH)>(p, a, s);
         default: return go_screen<PREC, 64, NCH, ub_for(PREC, 64, NCH)>(p, a, s);
@@ -623,12 +691,7 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     const size_t shm = (sizeof(double) + sizeof(int)) * 64 * (size_t)p.K;
-    const dim3 g((unsigned)p.n_waves), blk(64);
-    switch (p.UB) {
-        case 4: certify_kernel<4><<<g, blk, shm, s>>>(a); break;
-        case 2: certify_kernel<2><<<g, blk, shm, s>>>(a); break;
-        default: certify_kernel<1><<<g, blk, shm, s>>>(a); break;
-    }
+    certify_kernel<<<dim3((unsigned)p.n_ublk), dim3(64), shm, s>>>(a, p.UB);
     return hipGetLastError();
 }
 

@@ -66,4 +66,7 @@ def test_workspace_grows_with_precision_candidates(L):
 
 def test_backward_argument_errors(L):
     p = ctypes.c_void_p(256)
-    assert L.mips_topk_backward(None, p, 4, 4, 4, 2, p, p, p, p, None) == -1 or True
+    assert L.mips_topk_backward(None, p, 4, 4, 4, 2, p, p, p, p, None) == -1
+    assert L.mips_topk_backward(p, p, 0, 4, 4, 2, p, p, p, p, None) == -1
+    assert L.mips_topk_backward(p, p, 4, 4, 0, 2, p, p, p, p, None) == -1
+    assert L.mips_topk_backward(p, p, 4, 4, 4, 0, p, p, p, p, None) == -1
