@@ -18,6 +18,8 @@ FLAGS = [
     # never emit packed FP32 arithmetic (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
+    # keep matrix-core accumulators in VGPRs: the top-K epilogue reads them with VALU ops
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

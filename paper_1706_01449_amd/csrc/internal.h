@@ -17,9 +17,7 @@ enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
 __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap) {
     return prec == PREC_FP32
                ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
-               : ((prec == PREC_BF16 && nch_cap >= 8)
-                      ? (km <= 16 ? 2 : 1)
-                      : (km <= 10 ? 4 : (km <= 16 ? 3 : (km <= 32 ? 2 : 1))));
+               : ((prec == PREC_BF16 && nch_cap >= 8) ? 1 : (km <= 32 ? 2 : 1));
 }
 
 // Device-resident control block of one call.  Zeroed at the start of every

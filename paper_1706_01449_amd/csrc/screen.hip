@@ -128,6 +128,39 @@ __device__ __forceinline__ float pick_sorted(const float (&l)[KM], int idx) {
     return v;
 }
 
+// Insert x into a register list sorted in descending order, keeping its KM
+// largest entries: the new entry q is the median of old entries q-1, q and x
+// (one exact v_med3_f32 per slot, all independent).
+template <int KM>
+__device__ __forceinline__ void list_insert(float (&l)[KM], float x) {
+#pragma unroll
+    for (int q = KM - 1; q >= 1; --q) l[q] = __builtin_amdgcn_fmed3f(l[q - 1], l[q], x);
+    l[0] = fmaxf(l[0], x);
+}
+
+template <int KM>
+__device__ __forceinline__ void list_reset(float (&l)[KM], int K) {
+#pragma unroll
+    for (int q = 0; q < KM; ++q) l[q] = (q < KM - K) ? __builtin_inff() : -__builtin_inff();
+}
+
+// Valid lower bound on a user's K-th largest key from the two lanes' lists:
+// each lane's K-th largest entry, and the min over the two lanes of their
+// ceil(K/2)-th largest (together at least K values reach it).
+template <int KM>
+__device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
+    const float t = l[KM - 1];
+    const float th = pick_sorted(l, hidx);
+    const float tp = xor32_f(t), thp = xor32_f(th);
+    return fmaxf(fmaxf(t, tp), fminf(th, thp));
+}
+
+// Warm-up sets of per-slot maxima (16 slots per set) used to seed tau.
+__host__ __device__ constexpr int warm_sets(int km) {
+    return km <= 10 ? 1 : (km <= 16 ? 2 : (km <= 32 ? 3 : 4));
+}
+constexpr int kWarmRounds = 8;   // warm-up tiles per set
+
 // ---------------------------------------------------------------------------
 // The screen kernel.
 // ---------------------------------------------------------------------------
@@ -136,6 +169,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     typedef Prec<PREC> P;
     typedef typename P::Op Op;
     constexpr int E = P::E;
+    constexpr int S = warm_sets(KM);
     const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
     const int64_t w = blockIdx.x;
     const int nch = a.nch;
@@ -151,26 +185,25 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     const float Gmax = __uint_as_float(a.ctrl->gmax_bits);
 
     Op bu[UB][NCH];
-    float Au[UB], Bu[UB], slk[UB], tau[UB], Nup[UB];
+    float Au[UB], Bu[UB], slk[UB], tau[UB], tauf[UB], Nup[UB];
     float lst[UB][KM];
     int cnt[UB], uscale[UB];
     bool act[UB];
-    int64_t uid[UB];
+    int2* cptr[UB];
 
     // ---- prologue: load, quantise and measure this wave's users ----------
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
         bool valid;
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
-        uid[ub] = u;
         const float* urow = a.U + u * a.f;
         double s2 = 0.0, r2 = 0.0, q2 = 0.0;
         float amax = 0.0f;
         bool finite = true;
         if (valid) {
             for (int j = h * half; j < h * half + half && j < a.f; ++j) {
-                float x = urow[j];
-                finite = finite && __builtin_isfinite(x);
+                const float x = urow[j];
+                finite = finite && ((__float_as_uint(x) & 0x7f800000u) != 0x7f800000u);
                 s2 += (double)x * (double)x;
                 amax = fmaxf(amax, fabsf(x));
             }
@@ -187,16 +220,16 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             if (c < nch && valid) {
                 const int j0 = h * half + c * E;
                 if constexpr (PREC == PREC_FP32) {
-                    float x = (j0 < a.f) ? urow[j0] : 0.0f;
+                    const float x = (j0 < a.f) ? urow[j0] : 0.0f;
                     op = __builtin_bit_cast(Op, x);
                 } else if constexpr (PREC == PREC_BF16) {
                     uint32_t wd[4];
 #pragma unroll
                     for (int e = 0; e < 8; e += 2) {
-                        float x0 = (j0 + e < a.f) ? urow[j0 + e] : 0.0f;
-                        float x1 = (j0 + e + 1 < a.f) ? urow[j0 + e + 1] : 0.0f;
-                        uint16_t b0 = f32_to_bf16_bits(x0), b1 = f32_to_bf16_bits(x1);
-                        double d0 = bf16_bits_to_f32(b0), d1 = bf16_bits_to_f32(b1);
+                        const float x0 = (j0 + e < a.f) ? urow[j0 + e] : 0.0f;
+                        const float x1 = (j0 + e + 1 < a.f) ? urow[j0 + e + 1] : 0.0f;
+                        const uint16_t b0 = f32_to_bf16_bits(x0), b1 = f32_to_bf16_bits(x1);
+                        const double d0 = bf16_bits_to_f32(b0), d1 = bf16_bits_to_f32(b1);
                         r2 += ((double)x0 - d0) * ((double)x0 - d0) + ((double)x1 - d1) * ((double)x1 - d1);
                         q2 += d0 * d0 + d1 * d1;
                         wd[e / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
@@ -209,9 +242,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         uint32_t word = 0;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            float x = (j0 + e + q < a.f) ? urow[j0 + e + q] : 0.0f;
-                            uint32_t byte = e4m3_encode(__builtin_ldexpf(x, -k));
-                            double d = __builtin_ldexp((double)e4m3_decode(byte), k);
+                            const float x = (j0 + e + q < a.f) ? urow[j0 + e + q] : 0.0f;
+                            const uint32_t byte = e4m3_encode(__builtin_ldexpf(x, -k));
+                            const double d = __builtin_ldexp((double)e4m3_decode(byte), k);
                             r2 += ((double)x - d) * ((double)x - d);
                             q2 += d * d;
                             word |= byte << (8 * q);
@@ -253,19 +286,13 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         act[ub] = valid && !degenerate;
         tau[ub] = ninf;
         cnt[ub] = 0;
-#pragma unroll
-        for (int q = 0; q < KM; ++q) lst[ub][q] = (q < KM - a.K) ? pinf : ninf;
+        cptr[ub] = a.cand + (((w * UB + ub) * a.cap) << 6) + lane;
+        list_reset(lst[ub], a.K);
     }
 
     // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
     const int hidx = KM - (a.K / 2) - 1;
-
-    // ---- item sweep ------------------------------------------------------
-    // Two-stage software pipeline: while the VALU runs the top-K epilogue of
-    // tile b, the matrix cores already work on tile b+1 (second accumulator
-    // set) and the operands of tile b+2 are in flight.
     const int64_t n_blk = a.n_blk;
-    int64_t b_done = n_blk;       // tiles visited (the walk may stop early)
     const int* clist = a.walk ? a.lists + (int64_t)cluster * a.n_i : nullptr;
 
     // This lane's A-operand chunks of tile b (row n), the row's item index
@@ -288,7 +315,10 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         }
     };
 
-    auto mma_tile = [&](const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB]) __attribute__((always_inline)) {
+    // Score tile: acc[ub] = items (rows) x users (columns); rows past the
+    // last item are set to -inf.
+    auto score_tile = [&](int64_t b, const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB])
+        __attribute__((always_inline)) {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
             floatx16_t z = {};
@@ -297,59 +327,87 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             for (int c = 0; c < NCH; ++c)
                 if (c < nch) acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
         }
+        if ((b + 1) * kTile > a.n_i) {
+#pragma unroll
+            for (int ub = 0; ub < UB; ++ub)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (b * kTile + 8 * (r >> 2) + 4 * h + (r & 3) >= a.n_i) acc[ub][r] = ninf;
+        }
     };
+
+    // ---- warm-up: seed tau from per-slot maxima of the leading tiles -----
+    // Slot (s, r) keeps the max over tiles b = s (mod S) of this lane's row r:
+    // each slot max is the screened score of one distinct item, so the K-th
+    // largest of their lower bounds (over the user's two lanes) is a valid
+    // lower bound on the user's K-th largest key.  The leading tiles hold the
+    // largest-norm items (brute force) or the best-bound items (walk).
+    {
+        float gm[UB][S * 16];
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub)
+#pragma unroll
+            for (int q = 0; q < S * 16; ++q) gm[ub][q] = ninf;
+        for (int rd = 0; rd < kWarmRounds; ++rd) {
+#pragma unroll
+            for (int sidx = 0; sidx < S; ++sidx) {
+                const int64_t b = (int64_t)rd * S + sidx;
+                if (b < n_blk) {
+                    Op ai[NCH];
+                    int it = -1, sc = 127;
+                    load_tile(b, ai, it, sc);
+                    floatx16_t acc[UB];
+                    score_tile(b, ai, sc, acc);
+#pragma unroll
+                    for (int ub = 0; ub < UB; ++ub)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            gm[ub][sidx * 16 + r] = fmaxf(gm[ub][sidx * 16 + r], acc[ub][r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub) {
+            // every warm-up item has e <= A Cmax + B Gmax + slack
+            const float ew = fmaf(Au[ub], Cmax, fmaf(Bu[ub], Gmax, slk[ub]));
+#pragma unroll
+            for (int q = 0; q < S * 16; ++q) list_insert(lst[ub], gm[ub][q] - ew);
+            tau[ub] = list_tau(lst[ub], hidx);
+            list_reset(lst[ub], a.K);
+            tauf[ub] = act[ub] ? tau[ub] : pinf;
+        }
+    }
 
     // Streaming top-K over tile b; returns false once every user of a walk
     // wave has stopped.
     auto epi_tile = [&](int64_t b, floatx16_t (&acc)[UB], int item) __attribute__((always_inline)) -> bool {
         const float2 bm = a.walk ? a.cblockmax[(int64_t)cluster * n_blk + b] : a.blockmax[b];
-        const bool last = (b + 1) * kTile > a.n_i;
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
-            if (last) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t pos = b * kTile + 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (pos >= a.n_i) acc[ub][r] = __builtin_nanf("");  // never passes a compare
-                }
-            }
             const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
-            const float thr = act[ub] ? tau[ub] - ee : pinf;
+            const float thr = tauf[ub] - ee;
             float m = acc[ub][0];
 #pragma unroll
             for (int r = 1; r < 16; ++r) m = fmaxf(m, acc[ub][r]);
             if (ballot(m >= thr)) {
-                const int64_t ublk = w * UB + ub;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const float v = acc[ub][r];
-                    const bool hit = v >= thr;
+                    const bool hit = (v >= thr) && (v > ninf);
                     if (ballot(hit)) {
                         // item index of output row 8g + 4h + q, held by lane (row)
                         const int row = 8 * (r >> 2) + 4 * h + (r & 3);
                         const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
                         if (hit) {
-                            float x = v - ee;
-#pragma unroll
-                            for (int q = 0; q < KM; ++q) {
-                                const float hi = fmaxf(lst[ub][q], x);
-                                x = fminf(lst[ub][q], x);
-                                lst[ub][q] = hi;
-                            }
+                            list_insert(lst[ub], v - ee);
                             if (cnt[ub] < a.cap)
-                                a.cand[((ublk * a.cap + cnt[ub]) << 6) + lane] =
-                                    make_int2(__float_as_int(v), orig);
+                                cptr[ub][(int64_t)cnt[ub] << 6] = make_int2(__float_as_int(v), orig);
                             cnt[ub] += 1;
                         }
                     }
                 }
-                // Valid lower bounds on the user's K-th largest key: each
-                // lane's own K-th largest, and min over the two lanes of their
-                // ceil(K/2)-th largest (together at least K values reach it).
-                const float t = lst[ub][KM - 1];
-                const float th = pick_sorted(lst[ub], hidx);
-                const float tp = xor32_f(t), thp = xor32_f(th);
-                tau[ub] = fmaxf(tau[ub], fmaxf(fmaxf(t, tp), fminf(th, thp)));
+                tau[ub] = fmaxf(tau[ub], list_tau(lst[ub], hidx));
+                tauf[ub] = act[ub] ? tau[ub] : pinf;
             }
         }
         if (!a.walk) return true;
@@ -363,7 +421,10 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
 #pragma unroll
             for (int ub = 0; ub < UB; ++ub) {
-                if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) act[ub] = false;
+                if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) {
+                    act[ub] = false;
+                    tauf[ub] = pinf;
+                }
                 any = any || act[ub];
             }
         } else {
@@ -373,29 +434,25 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         return ballot(any) != 0;
     };
 
-    Op oA[NCH], oB[NCH];
-    int itA = -1, itB = -1, scA = 127, scB = 127;
-    floatx16_t accA[UB], accB[UB];
-    if (n_blk > 0) {
-        load_tile(0, oA, itA, scA);
-        mma_tile(oA, scA, accA);
-    }
-    if (n_blk > 1) load_tile(1, oB, itB, scB);
-    for (int64_t b = 0; b < n_blk; b += 2) {
-        // accA: tile b issued; oB: operands of tile b+1 in flight
-        const int eA = itA;
-        if (b + 1 < n_blk) mma_tile(oB, scB, accB);
-        if (b + 2 < n_blk) load_tile(b + 2, oA, itA, scA);
-        if (!epi_tile(b, accA, eA)) { b_done = b + 1; break; }
-        if (b + 1 >= n_blk) break;
-        // accB: tile b+1 issued; oA: operands of tile b+2 in flight
-        const int eB = itB;
-        if (b + 2 < n_blk) mma_tile(oA, scA, accA);
-        if (b + 3 < n_blk) load_tile(b + 3, oB, itB, scB);
-        if (!epi_tile(b + 1, accB, eB)) { b_done = b + 2; break; }
+    // ---- item sweep: operands of the next tile are loaded one tile ahead --
+    int64_t b_done = n_blk;       // tiles visited (the walk may stop early)
+    {
+        Op oA[NCH], oB[NCH];
+        int itA = -1, itB = -1, scA = 127, scB = 127;
+        floatx16_t acc[UB];
+        if (n_blk > 0) load_tile(0, oA, itA, scA);
+        for (int64_t b = 0; b < n_blk; b += 2) {
+            if (b + 1 < n_blk) load_tile(b + 1, oB, itB, scB);
+            score_tile(b, oA, scA, acc);
+            if (!epi_tile(b, acc, itA)) { b_done = b + 1; break; }
+            if (b + 1 >= n_blk) break;
+            if (b + 2 < n_blk) load_tile(b + 2, oA, itA, scA);
+            score_tile(b + 1, oB, scB, acc);
+            if (!epi_tile(b + 1, acc, itB)) { b_done = b + 2; break; }
+        }
     }
 
-    // ---- epilogue: hand the per-user state to certification --------------
+    // ---- hand the per-user state to certification -------------------------
     unsigned long long visited = 0;
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
