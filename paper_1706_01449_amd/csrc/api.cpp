@@ -83,19 +83,24 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
     p.n_u = n_u;
     p.n_i = n_i;
     p.fast = (K <= 64 && f <= 128);
+    // Factor chunks per matrix-core instruction sequence: the compiled chunk
+    // count is the smallest one that covers f; factors past f are zero.
     if (prec == PREC_FP32) {
-        p.f_pad = (f + 1) & ~1;
-        p.nch = p.f_pad / 2;
-        p.NCH = p.nch <= 8 ? 8 : (p.nch <= 32 ? 32 : 64);
+        const int need = (f + 1) / 2;                       // 2 factors per 32x32x2 step
+        static const int opts[] = {8, 16, 25, 32, 50, 64};
+        p.NCH = 64;
+        for (int o : opts) if (o >= need) { p.NCH = o; break; }
+        p.f_pad = 2 * p.NCH;
     } else if (prec == PREC_BF16) {
-        p.f_pad = (f + 15) & ~15;
-        p.nch = p.f_pad / 16;
-        p.NCH = p.nch <= 2 ? 2 : (p.nch <= 4 ? 4 : 8);
+        const int need = (f + 15) / 16;                     // 16 factors per 32x32x16 step
+        p.NCH = need <= 1 ? 1 : (need <= 2 ? 2 : (need <= 4 ? 4 : 8));
+        p.f_pad = 16 * p.NCH;
     } else {
-        p.f_pad = (f + 63) & ~63;
-        p.nch = p.f_pad / 64;
-        p.NCH = p.nch <= 1 ? 1 : 2;
+        const int need = (f + 63) / 64;                     // 64 factors per 32x32x64 step
+        p.NCH = need <= 1 ? 1 : 2;
+        p.f_pad = 64 * p.NCH;
     }
+    p.nch = p.NCH;
     p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 10 ? 10 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64))));
     p.UB = ub_for(prec, p.KM, p.NCH);
     // Candidate slots per lane (half a user's items): room for the K-list

@@ -130,6 +130,9 @@ constexpr int kFallbackMaxK = 4096;
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s);
 hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_screen_fp32(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_screen_bf16(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_screen_fp8(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s);

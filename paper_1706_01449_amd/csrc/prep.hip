@@ -140,6 +140,7 @@ __global__ void __launch_bounds__(64) item_pack_kernel(ItemPrepArgs a) {
     const int lane = threadIdx.x, m = lane & 31, h = lane >> 5;
     const int64_t p = b * kTile + m;
     const int item = (p < a.n_i) ? a.perm[p] : -1;
+    if (p >= a.n_i && h == 0) a.perm[p] = -1;   // padded positions: no item
     const int half = a.f_pad / 2;
     if (PREC == PREC_BF16) {
         const uint4* src = (const uint4*)a.qrow;

@@ -29,6 +29,8 @@
 // accumulation); for the float32 screen A_u = (f 2^-52 + gamma) ||u||, B = 0.
 // A per-user slack (2^-20 of the largest magnitude involved) absorbs the
 // float32 rounding of every threshold and bound computed here.
+#pragma once
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -164,7 +166,7 @@ constexpr int kWarmRounds = 8;   // warm-up tiles per set
 // ---------------------------------------------------------------------------
 // The screen kernel.
 // ---------------------------------------------------------------------------
-template <int PREC, int KM, int NCH, int UB>
+template <int PREC, int KM, int NCH, int UB, bool WALK>
 __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     typedef Prec<PREC> P;
     typedef typename P::Op Op;
@@ -172,12 +174,11 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     constexpr int S = warm_sets(KM);
     const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
     const int64_t w = blockIdx.x;
-    const int nch = a.nch;
     const int half = a.f_pad / 2;
     const float ninf = -__builtin_inff(), pinf = __builtin_inff();
 
     int4 tile = make_int4(0, 0, 0, 0);
-    if (a.walk) tile = a.tiles[w];
+    if (WALK) tile = a.tiles[w];
     const int cluster = tile.x;
 
     const float Cmax = __uint_as_float(a.ctrl->cmax_bits);
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             Op op = P::zero();
-            if (c < nch && valid) {
+            if (valid) {
                 const int j0 = h * half + c * E;
                 if constexpr (PREC == PREC_FP32) {
                     const float x = (j0 < a.f) ? urow[j0] : 0.0f;
@@ -293,24 +294,30 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
     const int hidx = KM - (a.K / 2) - 1;
     const int64_t n_blk = a.n_blk;
-    const int* clist = a.walk ? a.lists + (int64_t)cluster * a.n_i : nullptr;
+    const int* clist = WALK ? a.lists + (int64_t)cluster * a.n_i_pad : nullptr;
+    // per-tile bound maxima (prefetched with the tile operands)
+    const float2* bmax = WALK ? a.cblockmax + (int64_t)cluster * n_blk : a.blockmax;
 
     // This lane's A-operand chunks of tile b (row n), the row's item index
     // (-1 past the end) and, for E4M3, the row's E8M0 scale byte.
-    auto load_tile = [&](int64_t b, Op (&ai)[NCH], int& item, int& iscale) __attribute__((always_inline)) {
+    auto load_tile = [&](int64_t b, Op (&ai)[NCH], int& item, int& iscale, float2& bm)
+        __attribute__((always_inline)) {
         const int64_t p = b * kTile + n;
-        if (!a.walk) {
+        bm = bmax[b];
+        if constexpr (!WALK) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
-                if (c < nch) ai[c] = P::load_packed(a.packed, b, c, nch, lane);
-            item = (p < a.n_i) ? a.perm[p] : -1;
+                ai[c] = P::load_packed(a.packed, b, c, NCH, lane);
+            item = a.perm[p];                       // -1 past the last item
             if (PREC == PREC_FP8) iscale = a.pscale[p];
         } else {
-            item = (p < a.n_i) ? clist[p] : -1;
+            item = clist[p];                        // -1 past the last item
+            const int64_t row = item >= 0 ? item : 0;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (c < nch) ai[c] = (item >= 0) ? P::load_row(a.qrow, item, a.f_pad, h * half + c * E)
-                                                 : P::zero();
+            for (int c = 0; c < NCH; ++c) {
+                ai[c] = P::load_row(a.qrow, row, a.f_pad, h * half + c * E);
+                if (item < 0) ai[c] = P::zero();
+            }
             if (PREC == PREC_FP8) iscale = (item >= 0) ? a.kexp[item] + 127 : 127;
         }
     };
@@ -325,7 +332,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             acc[ub] = z;
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
-                if (c < nch) acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
+                acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
         }
         if ((b + 1) * kTile > a.n_i) {
 #pragma unroll
@@ -355,7 +362,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 if (b < n_blk) {
                     Op ai[NCH];
                     int it = -1, sc = 127;
-                    load_tile(b, ai, it, sc);
+                    float2 bmw;
+                    load_tile(b, ai, it, sc, bmw);
                     floatx16_t acc[UB];
                     score_tile(b, ai, sc, acc);
 #pragma unroll
@@ -380,8 +388,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // Streaming top-K over tile b; returns false once every user of a walk
     // wave has stopped.
-    auto epi_tile = [&](int64_t b, floatx16_t (&acc)[UB], int item) __attribute__((always_inline)) -> bool {
-        const float2 bm = a.walk ? a.cblockmax[(int64_t)cluster * n_blk + b] : a.blockmax[b];
+    auto epi_tile = [&](int64_t b, floatx16_t (&acc)[UB], int item, float2 bm)
+        __attribute__((always_inline)) -> bool {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
             const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
@@ -410,7 +418,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 tauf[ub] = act[ub] ? tau[ub] : pinf;
             }
         }
-        if (!a.walk) return true;
+        if constexpr (!WALK) return true;
         // Stop test after this tile (Section III-C): every unvisited item i has
         // key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is sorted,
         // so the next entry's bound covers all of them.
@@ -434,21 +442,31 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         return ballot(any) != 0;
     };
 
-    // ---- item sweep: operands of the next tile are loaded one tile ahead --
+    // ---- item sweep --------------------------------------------------------
+    // Operands are loaded two tiles ahead into alternating register sets; the
+    // loads are unconditional (tile index clamped to the last tile) so the
+    // loop body is straight-line code with exact wait counts.
     int64_t b_done = n_blk;       // tiles visited (the walk may stop early)
-    {
+    if (n_blk > 0) {
+        const int64_t last = n_blk - 1;
         Op oA[NCH], oB[NCH];
         int itA = -1, itB = -1, scA = 127, scB = 127;
+        float2 bmA, bmB;
         floatx16_t acc[UB];
-        if (n_blk > 0) load_tile(0, oA, itA, scA);
+        load_tile(0, oA, itA, scA, bmA);
+        load_tile(n_blk > 1 ? 1 : 0, oB, itB, scB, bmB);
         for (int64_t b = 0; b < n_blk; b += 2) {
-            if (b + 1 < n_blk) load_tile(b + 1, oB, itB, scB);
             score_tile(b, oA, scA, acc);
-            if (!epi_tile(b, acc, itA)) { b_done = b + 1; break; }
+            const int eA = itA;
+            const float2 mA = bmA;
+            load_tile(b + 2 < last ? b + 2 : last, oA, itA, scA, bmA);
+            if (!epi_tile(b, acc, eA, mA)) { b_done = b + 1; break; }
             if (b + 1 >= n_blk) break;
-            if (b + 2 < n_blk) load_tile(b + 2, oA, itA, scA);
             score_tile(b + 1, oB, scB, acc);
-            if (!epi_tile(b + 1, acc, itB)) { b_done = b + 2; break; }
+            const int eB = itB;
+            const float2 mB = bmB;
+            load_tile(b + 3 < last ? b + 3 : last, oB, itB, scB, bmB);
+            if (!epi_tile(b + 1, acc, eB, mB)) { b_done = b + 2; break; }
         }
     }
 
@@ -469,248 +487,12 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     if (lane == 0 && visited) atomicAdd(&a.ctrl->visited, visited);
 }
 
-// ---------------------------------------------------------------------------
-// Certification: keep the candidates whose upper bound reaches tau_u,
-// rescore them in float64 (left to right), and emit the first K by
-// (key desc, item index asc).  Same wave/user mapping as the screen.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
-    return ka > kb || (ka == kb && ia < ib);
-}
-
-// float64 key of (u, i): left-to-right sum over the factors, read two floats
-// at a time when both rows are 8-byte aligned (f even).
-__device__ __forceinline__ double dot64_rows(const float* __restrict__ u,
-                                             const float* __restrict__ v, int f) {
-    double acc = 0.0;
-    if ((f & 1) == 0) {
-        const float2* u2 = (const float2*)u;
-        const float2* v2 = (const float2*)v;
-        for (int j = 0; j < (f >> 1); ++j) {
-            const float2 x = u2[j], y = v2[j];
-            acc = __fma_rn((double)x.x, (double)y.x, acc);
-            acc = __fma_rn((double)x.y, (double)y.y, acc);
-        }
-        return acc;
-    }
-    return dot64(u, v, f);
-}
-
-// One wave per block of 32 users (same lane mapping as the screen: lane l
-// holds half l/32 of user l%32's candidates).
-__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a, int UB) {
-    extern __shared__ unsigned char smem[];
-    const int K = a.K;
-    double* skey = (double*)smem;                       // [64][K]
-    int* sidx = (int*)(smem + sizeof(double) * 64 * K); // [64][K]
-    __shared__ int scnt[64];
-    const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
-    const int64_t ublk = blockIdx.x;
-    const int64_t w = ublk / UB;
-    const int ub = (int)(ublk - w * UB);
-    int4 tile = make_int4(0, 0, 0, 0);
-    if (a.walk) tile = a.tiles[w];
-    double* mykey = skey + lane * K;
-    int* myidx = sidx + lane * K;
-
-    bool valid;
-    const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
-    const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
-    const bool flagged = valid ? (a.uflag[u] != 0) : true;
-    const float4 us = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const bool bad = c > a.cap;
-    int kept = 0;
-    unsigned long long st_resc = 0;
-    double st_abs = 0.0, st_rel = 0.0;
-    if (!flagged) {
-        const float* urow = a.U + u * a.f;
-        const int cm = min(c, a.cap);
-        const int2* cbase = a.cand + ((ublk * a.cap) << 6) + lane;
-        constexpr int CH = 4;     // candidates fetched together
-        for (int s0 = 0; s0 < cm; s0 += CH) {
-            int2 e[CH];
-            float Ci[CH], Gi[CH];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) e[q] = (s0 + q < cm) ? cbase[(int64_t)(s0 + q) << 6] : make_int2(0, -1);
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                Ci[q] = (e[q].y >= 0) ? a.Corig[e[q].y] : 0.0f;
-                Gi[q] = (e[q].y >= 0) ? a.Gorig[e[q].y] : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int item = e[q].y;
-                if (item < 0) continue;
-                const float sv = __int_as_float(e[q].x);
-                const float eb = fmaf(us.x, Ci[q], fmaf(us.y, Gi[q], us.z));
-                if (!(sv + eb >= us.w)) continue;
-                const double key = dot64_rows(urow, a.I + (int64_t)item * a.f, a.f);
-                const double err = fabs((double)sv - key);
-                st_abs = fmax(st_abs, err);
-                const double scale = (us.y > 0.0f ? (double)us.y : (double)us.x) * (double)Ci[q];
-                if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
-                ++st_resc;
-                // insert into this lane's sorted top-K list
-                const int len = kept < K ? kept : K;
-                ++kept;
-                if (len == K && !before(key, item, mykey[K - 1], myidx[K - 1])) continue;
-                int pos = (len < K) ? len : K - 1;
-                while (pos > 0 && before(key, item, mykey[pos - 1], myidx[pos - 1])) {
-                    mykey[pos] = mykey[pos - 1];
-                    myidx[pos] = myidx[pos - 1];
-                    --pos;
-                }
-                mykey[pos] = key;
-                myidx[pos] = item;
-            }
-        }
-    }
-    const int own = kept < K ? kept : K;
-    scnt[lane] = own;
-    __syncthreads();
-    const int other = scnt[lane ^ 32];
-    const int tot = kept + xor32_i(kept);
-    const int bad_p = xor32_i((int)bad);   // all lanes exchange
-    const bool anybad = bad || (bad_p != 0);
-    const int ctot = c + xor32_i(c);
-    if (valid && !flagged) {
-        if (anybad || tot < K) {
-            if (h == 0) flag_user(a, u);
-        } else {
-            const double* pk = skey + (lane ^ 32) * K;
-            const int* pi = sidx + (lane ^ 32) * K;
-            for (int x = 0; x < own; ++x) {
-                const double kx = mykey[x];
-                const int ix = myidx[x];
-                int rank = x;   // own list is sorted
-                for (int y = 0; y < other; ++y) rank += before(pk[y], pi[y], kx, ix) ? 1 : 0;
-                if (rank < K) {
-                    a.out_idx[u * K + rank] = ix;
-                    a.out_score[u * K + rank] = kx;
-                }
-            }
-        }
-    }
-    // wave reductions of the statistics, one atomic each
-    unsigned long long st_cand = (!flagged) ? (unsigned long long)c : 0ull;
-    unsigned long long st_max = (valid && h == 0) ? (unsigned long long)ctot : 0ull;
-    for (int off = 32; off >= 1; off >>= 1) {
-        st_cand += __shfl_xor(st_cand, off);
-        st_resc += __shfl_xor(st_resc, off);
-        st_max = max(st_max, (unsigned long long)__shfl_xor(st_max, off));
-        st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
-        st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
-    }
-    if (lane == 0) {
-        if (st_cand) atomicAdd(&a.ctrl->cand_total, st_cand);
-        if (st_resc) atomicAdd(&a.ctrl->rescored, st_resc);
-        if (st_max) atomicMax(&a.ctrl->cand_max, st_max);
-        atomic_max_nonneg((double*)&a.ctrl->max_abs_err, st_abs);
-        atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Exact float64 fallback: all keys of a flagged user, radix selection of the
-// K-th (key desc, index asc), then ranks.  Used for users whose candidate
-// buffer overflowed, degenerate users (zero, non-finite, out of range) and
-// requests outside the screen's compiled shapes.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long ordered(double k) {
-    unsigned long long b = (unsigned long long)__double_as_longlong(k);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-
-__global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
-    __shared__ unsigned int hist[256];
-    __shared__ double skey[kFallbackMaxK];
-    __shared__ int sidx[kFallbackMaxK];
-    __shared__ unsigned long long s_prefix;
-    __shared__ unsigned int s_need, s_sel, s_wave[4];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const unsigned int count = a.ctrl->fb_count;
-    double* keys = a.keys + (int64_t)blockIdx.x * a.n_i;
-    const int K = a.K;
-    for (unsigned int t = blockIdx.x; t < count; t += gridDim.x) {
-        const int64_t u = a.flist[t];
-        const float* urow = a.U + u * a.f;
-        for (int64_t i = tid; i < a.n_i; i += 256) keys[i] = dot64(urow, a.I + i * a.f, a.f);
-        if (tid == 0) { s_prefix = 0ull; s_need = (unsigned)K; s_sel = 0u; }
-        __syncthreads();
-        unsigned long long mask = 0ull;
-        for (int pass = 7; pass >= 0; --pass) {
-            hist[tid] = 0u;
-            __syncthreads();
-            const unsigned long long prefix = s_prefix;
-            for (int64_t i = tid; i < a.n_i; i += 256) {
-                const unsigned long long m = ordered(keys[i]);
-                if ((m & mask) == prefix) atomicAdd(&hist[(m >> (8 * pass)) & 255u], 1u);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                unsigned int need = s_need, cum = 0u;
-                int d = 255;
-                for (; d > 0; --d) {
-                    if (cum + hist[d] >= need) break;
-                    cum += hist[d];
-                }
-                s_need = need - cum;
-                s_prefix = prefix | ((unsigned long long)d << (8 * pass));
-            }
-            mask |= 255ull << (8 * pass);
-            __syncthreads();
-        }
-        const unsigned long long T = s_prefix;
-        const unsigned int take_eq = s_need;   // items equal to T to take, lowest indices first
-        unsigned int eq_before = 0u;
-        for (int64_t base = 0; base < a.n_i; base += 256) {
-            const int64_t i = base + tid;
-            unsigned long long m = 0ull;
-            double k = 0.0;
-            if (i < a.n_i) { k = keys[i]; m = ordered(k); }
-            const bool gt = i < a.n_i && m > T;
-            const bool eq = i < a.n_i && m == T;
-            const unsigned long long bal = __builtin_amdgcn_ballot_w64(eq);
-            const unsigned int below = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-            if (lane == 0) s_wave[wv] = __builtin_popcountll(bal);
-            __syncthreads();
-            unsigned int rank = eq_before + below;
-            for (int q = 0; q < wv; ++q) rank += s_wave[q];
-            const unsigned int chunk_eq = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-            if (gt || (eq && rank < take_eq)) {
-                const unsigned int slot = atomicAdd(&s_sel, 1u);
-                if (slot < (unsigned)kFallbackMaxK) { skey[slot] = k; sidx[slot] = (int)i; }
-            }
-            eq_before += chunk_eq;
-            __syncthreads();
-        }
-        const int sel = (int)min(s_sel, (unsigned)K);
-        for (int s = tid; s < sel; s += 256) {
-            const double kx = skey[s];
-            const int ix = sidx[s];
-            int rank = 0;
-            for (int y = 0; y < sel; ++y) rank += before(skey[y], sidx[y], kx, ix) ? 1 : 0;
-            if (rank < K) {
-                a.out_idx[u * K + rank] = ix;
-                a.out_score[u * K + rank] = kx;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__global__ void flag_all_kernel(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl) {
-    int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (u < n_u) { uflag[u] = 1; flist[u] = (int)u; }
-    if (u == 0) ctrl->fb_count = (unsigned int)n_u;
-}
-
-// ---------------------------------------------------------------------------
-// Launchers.
-// ---------------------------------------------------------------------------
 template <int PREC, int KM, int NCH, int UB>
 static hipError_t go_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    screen_kernel<PREC, KM, NCH, UB><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
+    if (a.walk)
+        screen_kernel<PREC, KM, NCH, UB, true><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
+    else
+        screen_kernel<PREC, KM, NCH, UB, false><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -724,42 +506,6 @@ static hipError_t screen_km(const ScreenPlan& p, const ScreenArgs& a, hipStream_
         case 32: return go_screen<PREC, 32, NCH, ub_for(PREC, 32, NCH)>(p, a, s);
         default: return go_screen<PREC, 64, NCH, ub_for(PREC, 64, NCH)>(p, a, s);
     }
-}
-
-hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    if (p.prec == PREC_BF16) {
-        switch (p.NCH) {
-            case 2: return screen_km<PREC_BF16, 2>(p, a, s);
-            case 4: return screen_km<PREC_BF16, 4>(p, a, s);
-            default: return screen_km<PREC_BF16, 8>(p, a, s);
-        }
-    } else if (p.prec == PREC_FP8) {
-        switch (p.NCH) {
-            case 1: return screen_km<PREC_FP8, 1>(p, a, s);
-            default: return screen_km<PREC_FP8, 2>(p, a, s);
-        }
-    }
-    switch (p.NCH) {
-        case 8: return screen_km<PREC_FP32, 8>(p, a, s);
-        case 32: return screen_km<PREC_FP32, 32>(p, a, s);
-        default: return screen_km<PREC_FP32, 64>(p, a, s);
-    }
-}
-
-hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    const size_t shm = (sizeof(double) + sizeof(int)) * 64 * (size_t)p.K;
-    certify_kernel<<<dim3((unsigned)p.n_ublk), dim3(64), shm, s>>>(a, p.UB);
-    return hipGetLastError();
-}
-
-hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s) {
-    flag_all_kernel<<<dim3((unsigned)((n_u + 255) / 256)), dim3(256), 0, s>>>(n_u, uflag, flist, ctrl);
-    return hipGetLastError();
-}
-
-hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s) {
-    fallback_kernel<<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
-    return hipGetLastError();
 }
 
 }  // namespace mips
