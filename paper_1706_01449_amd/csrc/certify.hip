@@ -31,107 +31,165 @@ __device__ __forceinline__ double dot64_rows(const float* __restrict__ u,
     return dot64(u, v, f);
 }
 
-// One wave per block of 32 users (same lane mapping as the screen: lane l
-// holds half l/32 of user l%32's candidates).
-__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a, int UB) {
-    extern __shared__ unsigned char smem[];
-    const int K = a.K;
-    double* skey = (double*)smem;                       // [64][K]
-    int* sidx = (int*)(smem + sizeof(double) * 64 * K); // [64][K]
-    __shared__ int scnt[64];
+// Largest index t in [0, n) with off[t] <= j (off non-decreasing, off[0] = 0).
+__device__ __forceinline__ int seg_of(const int* off, int n, int j) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One wave per block of 32 users.  The screen left each lane l (user l%32,
+// half l/32) a list of candidates; here the whole wave works on them in
+// lockstep: (1) every candidate whose upper bound reaches the user's tau is
+// kept and binned per user in LDS, (2) the kept pairs are rescored in
+// float64 (user rows staged in LDS), (3) each kept pair's rank among its
+// user's kept pairs by (key desc, index asc) decides its output slot.
+// Users whose candidate lists or bins overflowed, or who kept fewer than K,
+// go to the exact fallback.
+__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a, int UB, int segcap) {
+    extern __shared__ double smem_d[];
+    const int f = a.f, K = a.K;
     const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
     const int64_t ublk = blockIdx.x;
     const int64_t w = ublk / UB;
     const int ub = (int)(ublk - w * UB);
     int4 tile = make_int4(0, 0, 0, 0);
     if (a.walk) tile = a.tiles[w];
-    double* mykey = skey + lane * K;
-    int* myidx = sidx + lane * K;
 
+    // LDS carve-up
+    double* segk = smem_d;                                  // [32][segcap] keys
+    int* segi = (int*)(segk + 32 * segcap);                 // [32][segcap] items
+    float* urow = (float*)(segi + 32 * segcap);             // [32][f] user rows
+    __shared__ float4 us[32];
+    __shared__ int uval[32], ucnt[32], uoff[33], ubad[32];
+    __shared__ int coff[65];
+    __shared__ int64_t uid_s[32];
+
+    // ---- users of this block ---------------------------------------------
     bool valid;
     const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
     const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
-    const bool flagged = valid ? (a.uflag[u] != 0) : true;
-    const float4 us = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const bool bad = c > a.cap;
-    int kept = 0;
-    unsigned long long st_resc = 0;
-    double st_abs = 0.0, st_rel = 0.0;
-    if (!flagged) {
-        const float* urow = a.U + u * a.f;
-        const int cm = min(c, a.cap);
-        const int2* cbase = a.cand + ((ublk * a.cap) << 6) + lane;
-        constexpr int CH = 4;     // candidates fetched together
-        for (int s0 = 0; s0 < cm; s0 += CH) {
-            int2 e[CH];
-            float Ci[CH], Gi[CH];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) e[q] = (s0 + q < cm) ? cbase[(int64_t)(s0 + q) << 6] : make_int2(0, -1);
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                Ci[q] = (e[q].y >= 0) ? a.Corig[e[q].y] : 0.0f;
-                Gi[q] = (e[q].y >= 0) ? a.Gorig[e[q].y] : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int item = e[q].y;
-                if (item < 0) continue;
-                const float sv = __int_as_float(e[q].x);
-                const float eb = fmaf(us.x, Ci[q], fmaf(us.y, Gi[q], us.z));
-                if (!(sv + eb >= us.w)) continue;
-                const double key = dot64_rows(urow, a.I + (int64_t)item * a.f, a.f);
-                const double err = fabs((double)sv - key);
-                st_abs = fmax(st_abs, err);
-                const double scale = (us.y > 0.0f ? (double)us.y : (double)us.x) * (double)Ci[q];
-                if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
-                ++st_resc;
-                // insert into this lane's sorted top-K list
-                const int len = kept < K ? kept : K;
-                ++kept;
-                if (len == K && !before(key, item, mykey[K - 1], myidx[K - 1])) continue;
-                int pos = (len < K) ? len : K - 1;
-                while (pos > 0 && before(key, item, mykey[pos - 1], myidx[pos - 1])) {
-                    mykey[pos] = mykey[pos - 1];
-                    myidx[pos] = myidx[pos - 1];
-                    --pos;
-                }
-                mykey[pos] = key;
-                myidx[pos] = item;
-            }
-        }
+    if (h == 0) {
+        const bool fl = valid ? (a.uflag[u] != 0) : true;
+        uval[n] = (valid && !fl) ? 1 : 0;
+        us[n] = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        ucnt[n] = 0;
+        ubad[n] = 0;
+        uid_s[n] = u;
     }
-    const int own = kept < K ? kept : K;
-    scnt[lane] = own;
     __syncthreads();
-    const int other = scnt[lane ^ 32];
-    const int tot = kept + xor32_i(kept);
-    const int bad_p = xor32_i((int)bad);   // all lanes exchange
-    const bool anybad = bad || (bad_p != 0);
-    const int ctot = c + xor32_i(c);
-    if (valid && !flagged) {
-        if (anybad || tot < K) {
-            if (h == 0) flag_user(a, u);
-        } else {
-            const double* pk = skey + (lane ^ 32) * K;
-            const int* pi = sidx + (lane ^ 32) * K;
-            for (int x = 0; x < own; ++x) {
-                const double kx = mykey[x];
-                const int ix = myidx[x];
-                int rank = x;   // own list is sorted
-                for (int y = 0; y < other; ++y) rank += before(pk[y], pi[y], kx, ix) ? 1 : 0;
-                if (rank < K) {
-                    a.out_idx[u * K + rank] = ix;
-                    a.out_score[u * K + rank] = kx;
-                }
+    if (c > a.cap && uval[n]) ubad[n] = 1;                   // either half overflowed
+    // lanes' candidate counts -> prefix offsets (skipping users not certified here)
+    const int cc = uval[n] ? min(c, a.cap) : 0;
+    {
+        int incl = cc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        coff[lane + 1] = incl;
+        if (lane == 0) coff[0] = 0;
+    }
+    // stage the user rows (row r of the block = user r)
+    for (int t = lane; t < 32 * f; t += 64) {
+        const int r = t / f, j = t - r * f;
+        urow[t] = uval[r] ? a.U[uid_s[r] * f + j] : 0.0f;
+    }
+    __syncthreads();
+    const int total = coff[64];
+
+    // ---- (1) filter -------------------------------------------------------
+    for (int j = lane; j < total; j += 64) {
+        const int l = seg_of(coff, 64, j);
+        const int slot = j - coff[l];
+        const int2 e = a.cand[((ublk * a.cap + slot) << 6) + l];
+        const int item = e.y;
+        const int r = l & 31;
+        const float4 s4 = us[r];
+        const float sv = __int_as_float(e.x);
+        const float eb = fmaf(s4.x, a.Corig[item], fmaf(s4.y, a.Gorig[item], s4.z));
+        if (sv + eb >= s4.w) {
+            const int k = atomicAdd(&ucnt[r], 1);
+            if (k < segcap) {
+                segi[r * segcap + k] = item;
+                segk[r * segcap + k] = (double)sv;   // screened score, replaced by the key
+            } else {
+                ubad[r] = 1;
             }
         }
     }
-    // wave reductions of the statistics, one atomic each
-    unsigned long long st_cand = (!flagged) ? (unsigned long long)c : 0ull;
-    unsigned long long st_max = (valid && h == 0) ? (unsigned long long)ctot : 0ull;
+    __syncthreads();
+    if (lane < 32) {
+        const int kept = min(ucnt[lane], segcap);
+        if (uval[lane] && kept < K) ubad[lane] = 1;
+        int incl = (uval[lane] && !ubad[lane]) ? kept : 0;
+        for (int off = 1; off < 32; off <<= 1) {
+            const int v = __shfl_up(incl, off, 32);
+            if (lane >= off) incl += v;
+        }
+        uoff[lane + 1] = incl;
+        if (lane == 0) uoff[0] = 0;
+    }
+    __syncthreads();
+    const int ktot = uoff[32];
+
+    // ---- (2) float64 rescore ----------------------------------------------
+    double st_abs = 0.0, st_rel = 0.0;
+    for (int j = lane; j < ktot; j += 64) {
+        const int r = seg_of(uoff, 32, j);
+        const int k = j - uoff[r];
+        const int item = segi[r * segcap + k];
+        const float* ur = urow + r * f;
+        const float* ir = a.I + (int64_t)item * f;
+        double acc = 0.0;
+        if ((f & 1) == 0) {
+            const float2* i2 = (const float2*)ir;
+            for (int q = 0; q < (f >> 1); ++q) {
+                const float2 y = i2[q];
+                acc = __fma_rn((double)ur[2 * q], (double)y.x, acc);
+                acc = __fma_rn((double)ur[2 * q + 1], (double)y.y, acc);
+            }
+        } else {
+            for (int q = 0; q < f; ++q) acc = __fma_rn((double)ur[q], (double)ir[q], acc);
+        }
+        const double sv = segk[r * segcap + k];
+        const double err = fabs(sv - acc);
+        st_abs = fmax(st_abs, err);
+        const float4 s4 = us[r];
+        const double scale = (s4.y > 0.0f ? (double)s4.y : (double)s4.x) * (double)a.Corig[item];
+        if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+        segk[r * segcap + k] = acc;
+    }
+    __syncthreads();
+
+    // ---- (3) ranks and output ---------------------------------------------
+    for (int j = lane; j < ktot; j += 64) {
+        const int r = seg_of(uoff, 32, j);
+        const int k = j - uoff[r];
+        const int nk = uoff[r + 1] - uoff[r];
+        const double kx = segk[r * segcap + k];
+        const int ix = segi[r * segcap + k];
+        int rank = 0;
+        for (int y = 0; y < nk; ++y)
+            rank += before(segk[r * segcap + y], segi[r * segcap + y], kx, ix) ? 1 : 0;
+        if (rank < K) {
+            const int64_t uu = uid_s[r];
+            a.out_idx[uu * K + rank] = ix;
+            a.out_score[uu * K + rank] = kx;
+        }
+    }
+    if (lane < 32 && uval[lane] && ubad[lane]) flag_user(a, uid_s[lane]);
+
+    // statistics: one atomic each per wave
+    unsigned long long st_cand = (unsigned long long)cc;
+    const int ctot = c + xor32_i(c);
+    unsigned long long st_max = (h == 0 && valid) ? (unsigned long long)ctot : 0ull;
+    unsigned long long st_resc = (lane == 0) ? (unsigned long long)ktot : 0ull;
     for (int off = 32; off >= 1; off >>= 1) {
         st_cand += __shfl_xor(st_cand, off);
-        st_resc += __shfl_xor(st_resc, off);
         st_max = max(st_max, (unsigned long long)__shfl_xor(st_max, off));
         st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
         st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
@@ -249,9 +307,47 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
     return launch_screen_fp32(p, a, s);
 }
 
+// Per-user bin of kept candidates in certification (LDS).
+// Largest dynamic LDS one workgroup of the certification kernel may use on
+// the current device (queried once; raised above the 64 KB default when the
+// device allows it).
+static size_t certify_lds_limit() {
+    static size_t limit = 0;
+    if (limit == 0) {
+        int dev = 0, v = 0;
+        size_t lim = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            lim = (size_t)v;
+        if (lim > 150 * 1024) lim = 150 * 1024;
+        limit = lim;
+    }
+    return limit;
+}
+
+// Bins hold the kept candidates of one user: room for K plus the screen's
+// usual surplus (the E4M3 screen keeps several times more), within the LDS
+// a workgroup may use.  A user whose bin overflows goes to the fallback.
+static int certify_segcap(const ScreenPlan& p) {
+    const int want = (p.prec == PREC_FP8) ? 8 * p.K + 192 : 2 * p.K + 48;
+    const size_t avail = certify_lds_limit() - 2048 - (size_t)32 * p.f * sizeof(float);
+    const int room = (int)(avail / (32 * (sizeof(double) + sizeof(int))));
+    return want < room ? want : room;
+}
+
+size_t certify_lds_bytes(const ScreenPlan& p) {
+    return (size_t)32 * certify_segcap(p) * (sizeof(double) + sizeof(int)) + (size_t)32 * p.f * sizeof(float);
+}
+
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    const size_t shm = (sizeof(double) + sizeof(int)) * 64 * (size_t)p.K;
-    certify_kernel<<<dim3((unsigned)p.n_ublk), dim3(64), shm, s>>>(a, p.UB);
+    const size_t shm = certify_lds_bytes(p);
+    if (shm > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)certify_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    certify_kernel<<<dim3((unsigned)p.n_ublk), dim3(64), shm, s>>>(a, p.UB, certify_segcap(p));
     return hipGetLastError();
 }
 
