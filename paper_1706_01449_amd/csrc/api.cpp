@@ -340,6 +340,7 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
     a.kc = p.kc;
     a.gamma = p.gamma;
     a.ctrl = ctrl;
+    a.want_stats = stats != nullptr;
     a.uflag = (int*)(ws + L.uflag);
     a.flist = (int*)(ws + L.flist);
     a.uscal = (float4*)(ws + L.uscal);

@@ -13,188 +13,155 @@ __device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
     return ka > kb || (ka == kb && ia < ib);
 }
 
-// float64 key of (u, i): left-to-right sum over the factors, read two floats
-// at a time when both rows are 8-byte aligned (f even).
-__device__ __forceinline__ double dot64_rows(const float* __restrict__ u,
-                                             const float* __restrict__ v, int f) {
+// float64 key of (u, i) summed left to right; the row loads are issued in
+// batches of 16 factors so that one memory latency covers 16 FMAs.
+__device__ __forceinline__ double key64(const float* __restrict__ u, const float* __restrict__ v,
+                                        int f) {
     double acc = 0.0;
+    int j = 0;
     if ((f & 1) == 0) {
         const float2* u2 = (const float2*)u;
         const float2* v2 = (const float2*)v;
-        for (int j = 0; j < (f >> 1); ++j) {
-            const float2 x = u2[j], y = v2[j];
-            acc = __fma_rn((double)x.x, (double)y.x, acc);
-            acc = __fma_rn((double)x.y, (double)y.y, acc);
-        }
-        return acc;
-    }
-    return dot64(u, v, f);
-}
-
-// Largest index t in [0, n) with off[t] <= j (off non-decreasing, off[0] = 0).
-__device__ __forceinline__ int seg_of(const int* off, int n, int j) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= j) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// One wave per block of 32 users.  The screen left each lane l (user l%32,
-// half l/32) a list of candidates; here the whole wave works on them in
-// lockstep: (1) every candidate whose upper bound reaches the user's tau is
-// kept and binned per user in LDS, (2) the kept pairs are rescored in
-// float64 (user rows staged in LDS), (3) each kept pair's rank among its
-// user's kept pairs by (key desc, index asc) decides its output slot.
-// Users whose candidate lists or bins overflowed, or who kept fewer than K,
-// go to the exact fallback.
-__global__ void __launch_bounds__(64) certify_kernel(const ScreenArgs a, int UB, int segcap) {
-    extern __shared__ double smem_d[];
-    const int f = a.f, K = a.K;
-    const int lane = threadIdx.x, n = lane & 31, h = lane >> 5;
-    const int64_t ublk = blockIdx.x;
-    const int64_t w = ublk / UB;
-    const int ub = (int)(ublk - w * UB);
-    int4 tile = make_int4(0, 0, 0, 0);
-    if (a.walk) tile = a.tiles[w];
-
-    // LDS carve-up
-    double* segk = smem_d;                                  // [32][segcap] keys
-    int* segi = (int*)(segk + 32 * segcap);                 // [32][segcap] items
-    float* urow = (float*)(segi + 32 * segcap);             // [32][f] user rows
-    __shared__ float4 us[32];
-    __shared__ int uval[32], ucnt[32], uoff[33], ubad[32];
-    __shared__ int coff[65];
-    __shared__ int64_t uid_s[32];
-
-    // ---- users of this block ---------------------------------------------
-    bool valid;
-    const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
-    const int c = valid ? a.cnt[(ublk << 6) + lane] : 0;
-    if (h == 0) {
-        const bool fl = valid ? (a.uflag[u] != 0) : true;
-        uval[n] = (valid && !fl) ? 1 : 0;
-        us[n] = valid ? a.uscal[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-        ucnt[n] = 0;
-        ubad[n] = 0;
-        uid_s[n] = u;
-    }
-    __syncthreads();
-    if (c > a.cap && uval[n]) ubad[n] = 1;                   // either half overflowed
-    // lanes' candidate counts -> prefix offsets (skipping users not certified here)
-    const int cc = uval[n] ? min(c, a.cap) : 0;
-    {
-        int incl = cc;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off);
-            if (lane >= off) incl += v;
-        }
-        coff[lane + 1] = incl;
-        if (lane == 0) coff[0] = 0;
-    }
-    // stage the user rows (row r of the block = user r)
-    for (int t = lane; t < 32 * f; t += 64) {
-        const int r = t / f, j = t - r * f;
-        urow[t] = uval[r] ? a.U[uid_s[r] * f + j] : 0.0f;
-    }
-    __syncthreads();
-    const int total = coff[64];
-
-    // ---- (1) filter -------------------------------------------------------
-    for (int j = lane; j < total; j += 64) {
-        const int l = seg_of(coff, 64, j);
-        const int slot = j - coff[l];
-        const int2 e = a.cand[((ublk * a.cap + slot) << 6) + l];
-        const int item = e.y;
-        const int r = l & 31;
-        const float4 s4 = us[r];
-        const float sv = __int_as_float(e.x);
-        const float eb = fmaf(s4.x, a.Corig[item], fmaf(s4.y, a.Gorig[item], s4.z));
-        if (sv + eb >= s4.w) {
-            const int k = atomicAdd(&ucnt[r], 1);
-            if (k < segcap) {
-                segi[r * segcap + k] = item;
-                segk[r * segcap + k] = (double)sv;   // screened score, replaced by the key
-            } else {
-                ubad[r] = 1;
+        for (; j + 16 <= f; j += 16) {
+            float2 x[8], y[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) { x[q] = u2[(j >> 1) + q]; y[q] = v2[(j >> 1) + q]; }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc = __fma_rn((double)x[q].x, (double)y[q].x, acc);
+                acc = __fma_rn((double)x[q].y, (double)y[q].y, acc);
             }
         }
     }
-    __syncthreads();
-    if (lane < 32) {
-        const int kept = min(ucnt[lane], segcap);
-        if (uval[lane] && kept < K) ubad[lane] = 1;
-        int incl = (uval[lane] && !ubad[lane]) ? kept : 0;
-        for (int off = 1; off < 32; off <<= 1) {
-            const int v = __shfl_up(incl, off, 32);
-            if (lane >= off) incl += v;
-        }
-        uoff[lane + 1] = incl;
-        if (lane == 0) uoff[0] = 0;
-    }
-    __syncthreads();
-    const int ktot = uoff[32];
+    for (; j < f; ++j) acc = __fma_rn((double)u[j], (double)v[j], acc);
+    return acc;
+}
 
-    // ---- (2) float64 rescore ----------------------------------------------
+// G lanes per user (a group, contiguous in the wave), EM kept pairs per lane.
+// The screen left each user two candidate lists (its two lanes' halves);
+// lane g of the group takes entries g, g+G, ... of their concatenation, keeps
+// those whose upper bound reaches tau_u, rescores them in float64 and writes
+// them to its LDS slots.  The rank of a kept pair among the group's kept
+// pairs by (key desc, index asc) is its output position.  A user goes to the
+// exact fallback when a candidate list overflowed, a lane kept more than EM
+// pairs, or fewer than K pairs were kept.
+template <int G, int EM>
+__global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB, int64_t n_ublk) {
+    __shared__ double skey[256 * EM];
+    __shared__ int sidx[256 * EM];
+    __shared__ int scnt[256];
+    const int t = threadIdx.x;
+    const int g = t & (G - 1);
+    const int gbase = t - g;                 // first thread of this group
+    const int64_t slotu = (blockIdx.x * (int64_t)256 + t) / G;   // user slot in screen order
+    const int64_t ublk = slotu >> 5;
+    const int n = (int)(slotu & 31);
+    const int K = a.K;
+
+    bool valid = false;
+    int64_t u = 0;
+    int c0 = 0, c1 = 0;
+    if (ublk < n_ublk) {
+        const int64_t w = ublk / UB;
+        const int ub = (int)(ublk - w * UB);
+        int4 tile = make_int4(0, 0, 0, 0);
+        if (a.walk) tile = a.tiles[w];
+        u = user_of(a, UB, w, ub, n, tile, &valid);
+        c0 = a.cnt[(ublk << 6) + n];
+        c1 = a.cnt[(ublk << 6) + n + 32];
+    }
+    const bool flagged = valid ? (a.uflag[u] != 0) : true;
+    bool bad = (c0 > a.cap) || (c1 > a.cap);
+    const int m0 = min(c0, a.cap), m1 = min(c1, a.cap);
+    const int tot = flagged ? 0 : m0 + m1;
+    int kept = 0;
     double st_abs = 0.0, st_rel = 0.0;
-    for (int j = lane; j < ktot; j += 64) {
-        const int r = seg_of(uoff, 32, j);
-        const int k = j - uoff[r];
-        const int item = segi[r * segcap + k];
-        const float* ur = urow + r * f;
-        const float* ir = a.I + (int64_t)item * f;
-        double acc = 0.0;
-        if ((f & 1) == 0) {
-            const float2* i2 = (const float2*)ir;
-            for (int q = 0; q < (f >> 1); ++q) {
-                const float2 y = i2[q];
-                acc = __fma_rn((double)ur[2 * q], (double)y.x, acc);
-                acc = __fma_rn((double)ur[2 * q + 1], (double)y.y, acc);
+    if (!flagged) {
+        const float4 us = a.uscal[u];
+        const float* urow = a.U + u * a.f;
+        // the user's two lists (lanes n and n+32 of its screen wave), lane-major
+        const int2* list0 = a.cand + ((ublk << 6) + n) * (int64_t)a.cap;
+        const int2* list1 = a.cand + ((ublk << 6) + n + 32) * (int64_t)a.cap;
+        for (int j0 = g; j0 < tot; j0 += 4 * G) {
+            int2 e[4];
+            float Ci[4], Gi[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + q * G;
+                e[q] = make_int2(0, -1);
+                if (j < tot) e[q] = (j < m0) ? list0[j] : list1[j - m0];
             }
-        } else {
-            for (int q = 0; q < f; ++q) acc = __fma_rn((double)ur[q], (double)ir[q], acc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int item = e[q].y;
+                Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
+                Gi[q] = (item >= 0) ? a.Gorig[item] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int item = e[q].y;
+                if (item < 0) continue;
+                const float sv = __int_as_float(e[q].x);
+                const float eb = fmaf(us.x, Ci[q], fmaf(us.y, Gi[q], us.z));
+                if (!(sv + eb >= us.w)) continue;
+                if (kept < EM) {
+                    const double key = key64(urow, a.I + (int64_t)item * a.f, a.f);
+                    const double err = fabs((double)sv - key);
+                    st_abs = fmax(st_abs, err);
+                    const double scale = (us.y > 0.0f ? (double)us.y : (double)us.x) * (double)Ci[q];
+                    if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+                    skey[t * EM + kept] = key;
+                    sidx[t * EM + kept] = item;
+                }
+                ++kept;
+            }
         }
-        const double sv = segk[r * segcap + k];
-        const double err = fabs(sv - acc);
-        st_abs = fmax(st_abs, err);
-        const float4 s4 = us[r];
-        const double scale = (s4.y > 0.0f ? (double)s4.y : (double)s4.x) * (double)a.Corig[item];
-        if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
-        segk[r * segcap + k] = acc;
+    }
+    if (kept > EM) bad = true;
+    scnt[t] = kept < EM ? kept : EM;
+    // group totals and flags
+    int gk = kept;
+    int gb = bad ? 1 : 0;
+    for (int off = G / 2; off >= 1; off >>= 1) {
+        gk += __shfl_xor(gk, off, G);
+        gb |= __shfl_xor(gb, off, G);
     }
     __syncthreads();
-
-    // ---- (3) ranks and output ---------------------------------------------
-    for (int j = lane; j < ktot; j += 64) {
-        const int r = seg_of(uoff, 32, j);
-        const int k = j - uoff[r];
-        const int nk = uoff[r + 1] - uoff[r];
-        const double kx = segk[r * segcap + k];
-        const int ix = segi[r * segcap + k];
-        int rank = 0;
-        for (int y = 0; y < nk; ++y)
-            rank += before(segk[r * segcap + y], segi[r * segcap + y], kx, ix) ? 1 : 0;
-        if (rank < K) {
-            const int64_t uu = uid_s[r];
-            a.out_idx[uu * K + rank] = ix;
-            a.out_score[uu * K + rank] = kx;
+    if (valid && !flagged) {
+        if (gb || gk < K) {
+            if (g == 0) flag_user(a, u);
+        } else {
+            const int own = scnt[t];
+            for (int x = 0; x < own; ++x) {
+                const double kx = skey[t * EM + x];
+                const int ix = sidx[t * EM + x];
+                int rank = 0;
+                for (int q = 0; q < G; ++q) {
+                    const int o = gbase + q;
+                    const int no = scnt[o];
+                    for (int y = 0; y < no; ++y)
+                        rank += before(skey[o * EM + y], sidx[o * EM + y], kx, ix) ? 1 : 0;
+                }
+                if (rank < K) {
+                    a.out_idx[u * K + rank] = ix;
+                    a.out_score[u * K + rank] = kx;
+                }
+            }
         }
     }
-    if (lane < 32 && uval[lane] && ubad[lane]) flag_user(a, uid_s[lane]);
-
-    // statistics: one atomic each per wave
-    unsigned long long st_cand = (unsigned long long)cc;
-    const int ctot = c + xor32_i(c);
-    unsigned long long st_max = (h == 0 && valid) ? (unsigned long long)ctot : 0ull;
-    unsigned long long st_resc = (lane == 0) ? (unsigned long long)ktot : 0ull;
+    if (!a.want_stats) return;
+    // statistics: reduce over the wave, one atomic each
+    unsigned long long st_cand = (g == 0 && !flagged) ? (unsigned long long)(c0 + c1) : 0ull;
+    unsigned long long st_max = (g == 0 && valid) ? (unsigned long long)(c0 + c1) : 0ull;
+    unsigned long long st_resc = (unsigned long long)(kept < EM ? kept : EM);
     for (int off = 32; off >= 1; off >>= 1) {
         st_cand += __shfl_xor(st_cand, off);
+        st_resc += __shfl_xor(st_resc, off);
         st_max = max(st_max, (unsigned long long)__shfl_xor(st_max, off));
         st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
         st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
     }
-    if (lane == 0) {
+    if ((t & 63) == 0) {
         if (st_cand) atomicAdd(&a.ctrl->cand_total, st_cand);
         if (st_resc) atomicAdd(&a.ctrl->rescored, st_resc);
         if (st_max) atomicMax(&a.ctrl->cand_max, st_max);
@@ -308,46 +275,20 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 }
 
 // Per-user bin of kept candidates in certification (LDS).
-// Largest dynamic LDS one workgroup of the certification kernel may use on
-// the current device (queried once; raised above the 64 KB default when the
-// device allows it).
-static size_t certify_lds_limit() {
-    static size_t limit = 0;
-    if (limit == 0) {
-        int dev = 0, v = 0;
-        size_t lim = 64 * 1024;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-            v > 0)
-            lim = (size_t)v;
-        if (lim > 150 * 1024) lim = 150 * 1024;
-        limit = lim;
-    }
-    return limit;
-}
-
-// Bins hold the kept candidates of one user: room for K plus the screen's
-// usual surplus (the E4M3 screen keeps several times more), within the LDS
-// a workgroup may use.  A user whose bin overflows goes to the fallback.
-static int certify_segcap(const ScreenPlan& p) {
-    const int want = (p.prec == PREC_FP8) ? 8 * p.K + 192 : 2 * p.K + 48;
-    const size_t avail = certify_lds_limit() - 2048 - (size_t)32 * p.f * sizeof(float);
-    const int room = (int)(avail / (32 * (sizeof(double) + sizeof(int))));
-    return want < room ? want : room;
-}
-
-size_t certify_lds_bytes(const ScreenPlan& p) {
-    return (size_t)32 * certify_segcap(p) * (sizeof(double) + sizeof(int)) + (size_t)32 * p.f * sizeof(float);
-}
-
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    const size_t shm = certify_lds_bytes(p);
-    if (shm > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)certify_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-    }
-    certify_kernel<<<dim3((unsigned)p.n_ublk), dim3(64), shm, s>>>(a, p.UB, certify_segcap(p));
+    // lanes per user G and kept pairs per lane: 64 pairs per user for the
+    // float32/bfloat16 screens at K <= 16, 256 for larger K or E4M3 at
+    // K <= 16, 1024 for E4M3 at larger K (its coarse screen keeps hundreds)
+    const bool fp8 = p.prec == PREC_FP8;
+    const int G = (!fp8 && p.K <= 16) ? 8 : ((fp8 && p.K > 16) ? 64 : 16);
+    const int64_t threads = p.n_ublk * 32 * G;
+    const dim3 grid((unsigned)((threads + 255) / 256)), blk(256);
+    if (G == 8)
+        certify_kernel<8, 8><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+    else if (G == 16)
+        certify_kernel<16, 16><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+    else
+        certify_kernel<64, 16><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
     return hipGetLastError();
 }
 

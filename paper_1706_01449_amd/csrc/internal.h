@@ -82,12 +82,13 @@ struct ScreenArgs {
     const float* Corig;       // ||i|| rounded up
     const float* Gorig;       // ||i - screen(i)|| + gamma ||screen(i)||, rounded up
     // per-call state
+    int want_stats;           // accumulate the optional statistics (atomics)
     Ctrl* ctrl;
     int* uflag;               // n_u: 0 normal, 1 on the fallback list
     int* flist;               // n_u: fallback list
     float4* uscal;            // n_u: (A_u, B_u, slack_u, tau_u)
     int* cnt;                 // n_ublk * 64 candidate counts
-    int2* cand;               // n_ublk * cap * 64 candidates (score bits, position)
+    int2* cand;               // n_ublk * 64 lists of cap candidates (score bits, item index)
     int32_t* out_idx;
     double* out_score;
 };

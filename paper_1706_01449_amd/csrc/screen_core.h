@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         act[ub] = valid && !degenerate;
         tau[ub] = ninf;
         cnt[ub] = 0;
-        cptr[ub] = a.cand + (((w * UB + ub) * a.cap) << 6) + lane;
+        cptr[ub] = a.cand + (((w * UB + ub) << 6) + lane) * (int64_t)a.cap;   // lane-major lists
         list_reset(lst[ub], a.K);
     }
 
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         if (hit) {
                             list_insert(lst[ub], v - ee);
                             if (cnt[ub] < a.cap)
-                                cptr[ub][(int64_t)cnt[ub] << 6] = make_int2(__float_as_int(v), orig);
+                                cptr[ub][cnt[ub]] = make_int2(__float_as_int(v), orig);
                             cnt[ub] += 1;
                         }
                     }
@@ -483,8 +483,10 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             visited += (unsigned long long)(b_done * kTile < a.n_i ? b_done * kTile : a.n_i);
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) visited += __shfl_xor(visited, off);
-    if (lane == 0 && visited) atomicAdd(&a.ctrl->visited, visited);
+    if (a.want_stats) {
+        for (int off = 32; off >= 1; off >>= 1) visited += __shfl_xor(visited, off);
+        if (lane == 0 && visited) atomicAdd(&a.ctrl->visited, visited);
+    }
 }
 
 template <int PREC, int KM, int NCH, int UB>
