@@ -178,7 +178,7 @@ static int check_common(int64_t n_u, int64_t n_i, int f, int K, int prec) {
     return MIPS_OK;
 }
 
-static int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stats* stats) {
+int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stats* stats) {
     Ctrl h{};
     hipError_t e = hipMemcpyAsync(&h, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -341,6 +341,7 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
     a.gamma = p.gamma;
     a.ctrl = ctrl;
     a.want_stats = stats != nullptr;
+    a.warm_rounds = 8;
     a.uflag = (int*)(ws + L.uflag);
     a.flist = (int*)(ws + L.flist);
     a.uscal = (float4*)(ws + L.uscal);
@@ -395,22 +396,3 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
 
 }  // extern "C"
 
-// Entry points implemented in later stages of the library.
-extern "C" {
-
-int mips_maximus_build(const float*, int64_t, const float*, int64_t, int32_t, int32_t, int32_t,
-                       uint64_t, int32_t, void*, mips_maximus_index** out_index) {
-    if (out_index) *out_index = nullptr;
-    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
-}
-size_t mips_maximus_query_workspace_size(const mips_maximus_index*, int32_t, int32_t) { return 0; }
-int mips_maximus_query(const mips_maximus_index*, int32_t, int32_t, int32_t*, double*, void*, size_t,
-                       void*, mips_stats*) {
-    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
-}
-void mips_maximus_free(mips_maximus_index*) {}
-int mips_maximus_export(const mips_maximus_index*, int32_t*, int32_t*, int64_t*, int64_t*, double*,
-                        double*, int32_t*, int32_t*, float*, void*) {
-    return fail(MIPS_ERR_UNSUPPORTED, "Maximus is not built yet");
-}
-}  // extern "C"

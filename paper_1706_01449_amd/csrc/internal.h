@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/mips.h"
+
 namespace mips {
 
 // Precision codes (same values as the public mips_precision enum).
@@ -70,6 +72,7 @@ struct ScreenArgs {
     const int* perm;          // sorted position -> item index
     // Maximus walk
     int walk;
+    int warm_rounds;          // warm-up rounds seeding tau (tiles per warm-up set)
     int shared_blocks;        // leading list tiles scored before any user may stop
     const int4* tiles;        // (cluster, first sorted user, user count, 0)
     const int* sorted_users;  // users grouped by cluster
@@ -161,6 +164,10 @@ private:
     hipEvent_t start_ = nullptr, stop_ = nullptr;
     bool active_ = false;
 };
+
+// Copies the control block to the host (synchronising `s`) and fills the
+// public statistics struct.
+int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stats* stats);
 
 // Plan selection (host only).
 bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t n_waves_override,

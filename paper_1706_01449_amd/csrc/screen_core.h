@@ -161,7 +161,6 @@ __device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
 __host__ __device__ constexpr int warm_sets(int km) {
     return km <= 10 ? 1 : (km <= 16 ? 2 : (km <= 32 ? 3 : 4));
 }
-constexpr int kWarmRounds = 8;   // warm-up tiles per set
 
 // ---------------------------------------------------------------------------
 // The screen kernel.
@@ -187,6 +186,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     Op bu[UB][NCH];
     float Au[UB], Bu[UB], slk[UB], tau[UB], tauf[UB], Nup[UB];
+    int64_t ustop[UB];            // walk: tiles visited before the user stopped
     float lst[UB][KM];
     int cnt[UB], uscale[UB];
     bool act[UB];
@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         act[ub] = valid && !degenerate;
         tau[ub] = ninf;
         cnt[ub] = 0;
+        ustop[ub] = -1;
         cptr[ub] = a.cand + (((w * UB + ub) << 6) + lane) * (int64_t)a.cap;   // lane-major lists
         list_reset(lst[ub], a.K);
     }
@@ -355,7 +356,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         for (int ub = 0; ub < UB; ++ub)
 #pragma unroll
             for (int q = 0; q < S * 16; ++q) gm[ub][q] = ninf;
-        for (int rd = 0; rd < kWarmRounds; ++rd) {
+        for (int rd = 0; rd < a.warm_rounds; ++rd) {
 #pragma unroll
             for (int sidx = 0; sidx < S; ++sidx) {
                 const int64_t b = (int64_t)rd * S + sidx;
@@ -432,6 +433,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) {
                     act[ub] = false;
                     tauf[ub] = pinf;
+                    ustop[ub] = b + 1;
                 }
                 any = any || act[ub];
             }
@@ -480,7 +482,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
         if (valid && h == 0) {
             a.uscal[u] = make_float4(Au[ub], Bu[ub], slk[ub], tau[ub]);
-            visited += (unsigned long long)(b_done * kTile < a.n_i ? b_done * kTile : a.n_i);
+            const int64_t tiles_seen = (ustop[ub] >= 0) ? ustop[ub] : b_done;
+            visited += (unsigned long long)(tiles_seen * kTile < a.n_i ? tiles_seen * kTile : a.n_i);
         }
     }
     if (a.want_stats) {
