@@ -50,6 +50,96 @@ def time_path(mips, torch, Ut, It, K, prec, steps, warmup):
     return (t1 - t0) / steps, phases, st, out
 
 
+def timed(torch, fn, reps):
+    """Median wall time of fn() in ms, synchronised (inputs resident)."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def extras(mips, torch, np, mipsgen, oracle_topk):
+    """The other rows of the hot path, each on its own synthetic workload."""
+    dev = torch.device("cuda:0")
+    out = {}
+    # --- Maximus on the clustered workload (480,000 x 17,770, f = 50, K = 10)
+    log("extras: maximus")
+    U, I = mipsgen.generate("clustered", 0)
+    Ut = torch.from_numpy(U).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    mx = {}
+    t_bmm = timed(torch, lambda: mips.bmm_topk(Ut, It, 10, "bf16"), 5)
+    for C in (8, 64, 256):
+        holder = {}
+        def build():
+            holder["ix"] = mips.maximus_build(Ut, It, C, 3, 0, 0)
+        tb = timed(torch, build, 3)
+        ix = holder["ix"]
+        tq = timed(torch, lambda: ix.query(10, "bf16"), 5)
+        idx, score, st = ix.query(10, "bf16", stats=True)
+        users = mipsgen.sample_users(U.shape[0], 200, seed=C)
+        ri, _ = oracle_topk.topk(U[users], I, 10)
+        mx[f"C{C}"] = {"build_ms": tb, "query_ms": tq, "end_to_end_ms": tb + tq,
+                       "users_per_s_query": U.shape[0] / (tq * 1e-3),
+                       "users_per_s_end_to_end": U.shape[0] / ((tb + tq) * 1e-3),
+                       "mean_items_visited": st["mean_items_visited"],
+                       "index_match_sampled": float(np.mean(np.all(idx.cpu().numpy()[users] == ri, 1)))}
+        del ix, holder
+    mx["bmm_bf16_ms_same_data"] = t_bmm
+    out["maximus_clustered_480000x17770_f50_K10"] = mx
+    del Ut, It, U, I
+    torch.cuda.empty_cache()
+    # --- precision form: 1,000,000 x 136,000, f = 100, K = 10
+    log("extras: precision form")
+    U, I = mipsgen.generate("precision", 0)
+    Ut = torch.from_numpy(U).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    pf = {}
+    users = mipsgen.sample_users(U.shape[0], 100, seed=1)
+    ri, rk = oracle_topk.topk(U[users], I, 10)
+    for prec in ("bf16", "fp8", "fp32"):
+        ws = torch.empty(mips.lib().mips_bmm_topk_workspace_size(U.shape[0], I.shape[0], 100, 10,
+                                                                  mips.PRECISIONS[prec]),
+                         dtype=torch.uint8, device=dev)
+        t = timed(torch, lambda: mips.bmm_topk(Ut, It, 10, prec, workspace=ws), 3)
+        idx, score, st = mips.bmm_topk(Ut, It, 10, prec, stats=True, workspace=ws)
+        gi = idx.cpu().numpy()[users]
+        gs = score.cpu().numpy()[users]
+        pf[prec] = {"ms": t, "users_per_s": U.shape[0] / (t * 1e-3),
+                    "index_match_sampled": float(np.mean(np.all(gi == ri, 1))),
+                    "max_score_err_sampled": float(np.max(np.abs(gs - rk))),
+                    "candidates_per_user": st["candidates_total"] / U.shape[0],
+                    "rescored_per_user": st["rescored_pairs"] / U.shape[0],
+                    "overflow_users": st["overflow_users"],
+                    "max_screen_abs_err": st["max_screen_abs_err"],
+                    "max_screen_rel_err": st["max_screen_rel_err"]}
+        del ws
+    out["precision_1000000x136000_f100_K10"] = pf
+    del Ut, It, U, I
+    torch.cuda.empty_cache()
+    # --- differentiation form: 65,536 x 100,000, f = 64, K = 32
+    log("extras: backward")
+    U, I = mipsgen.generate("grad", 0)
+    Ut = torch.from_numpy(U).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    idx, score = mips.bmm_topk(Ut, It, 32, "bf16")
+    G = torch.softmax(score.to(torch.float32), dim=1).contiguous()
+    tf = timed(torch, lambda: mips.bmm_topk(Ut, It, 32, "bf16"), 5)
+    tbk = timed(torch, lambda: mips.topk_backward(Ut, It, idx, G), 10)
+    pairs = U.shape[0] * 32
+    bytes_alg = pairs * 64 * 4 * 2 + U.shape[0] * 64 * 4 * 2 + I.shape[0] * 64 * 4
+    out["grad_65536x100000_f64_K32"] = {
+        "forward_ms": tf, "backward_ms": tbk,
+        "backward_pairs_per_s": pairs / (tbk * 1e-3),
+        "backward_algorithmic_GBps": bytes_alg / (tbk * 1e-3) / 1e9}
+    return out
+
+
 def cpu_baseline(U, I, K, seconds_target=15.0):
     """The oracle as it stands, on a bounded user sample, all host cores."""
     import numpy as np
@@ -78,6 +168,8 @@ def main():
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the Maximus / precision-form / backward measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -150,6 +242,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(U, I, K)
+    if not args.no_extras:
+        del Ut, It, out
+        torch.cuda.empty_cache()
+        line["extras"] = extras(mips, torch, np, mipsgen, oracle_topk)
     print(json.dumps(line), flush=True)
 
 
