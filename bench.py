@@ -23,6 +23,58 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"bf16": 2516.6, "fp8": 5033.2, "fp32": 157.3}
 
+# Sources whose content decides the screen kernel's machine code: measured
+# traffic is reported only while their hash matches the one recorded with it.
+SCREEN_SOURCES = ["include/mips.h", "paper_1706_01449_amd/csrc/internal.h",
+                  "paper_1706_01449_amd/csrc/device_common.h",
+                  "paper_1706_01449_amd/csrc/screen_core.h",
+                  "paper_1706_01449_amd/csrc/screen_bf16.hip",
+                  "paper_1706_01449_amd/csrc/api.cpp",
+                  "paper_1706_01449_amd/build.py"]
+TRAFFIC_FILE = "profiles/screen_kernel_mf_480000x17770_f50_bf16_K10_traffic.txt"
+
+
+def screen_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SCREEN_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per screen launch from the committed counter summary, or None
+    when the summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != screen_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -170,7 +222,17 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Maximus / precision-form / backward measurements")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the screen kernel sources and exit")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(screen_source_hash())
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    "--gpus above 1 is not supported"}))
@@ -231,7 +293,7 @@ def main():
         "config": {"workload": "mf_480000x17770_f50", "n_users": n_u, "n_items": n_i, "f": f,
                    "K": K, "precision": args.precision, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "screen_kernel",
+                     "frac": achieved / peak, "traffic": measured_traffic(), "kernel": "screen_kernel",
                      "kernel_ms": scr_ms},
         "phases_ms": {k: v[0] / max(1, v[1]) for k, v in ph_main.items() if v[1]},
         "fp32_screen": fp32,

@@ -107,7 +107,7 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
     // entries plus the items that pass before the threshold settles; the
     // coarser E4M3 screen keeps several times more.
     if (prec == PREC_FP8)
-        p.cap = std::max(256, 8 * p.KM + 64);
+        p.cap = std::max(512, 8 * p.KM + 64);
     else
         p.cap = std::max(64, 2 * p.KM + 32);
     // Test-only override of the candidate slots per lane (forces the overflow
@@ -121,7 +121,7 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
     p.n_i_pad = p.n_blk * 32;
     p.n_waves = (n_u + 32 * p.UB - 1) / (32 * p.UB);
     p.n_ublk = p.n_waves * p.UB;
-    p.fb_grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, n_u));
+    p.fb_grid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n_u));
     const double n = (prec == PREC_FP32) ? (double)(p.f_pad + 1) : (double)p.f_pad;
     const double g = n * 0x1p-22 / (1.0 - n * 0x1p-22);
     p.gamma = (float)(g * (1.0 + 0x1p-20));

@@ -79,6 +79,11 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
     if (!flagged) {
         const float4 us = a.uscal[u];
         const float* urow = a.U + u * a.f;
+        double unorm = 0.0;   // ||u||, for the relative error statistic only
+        if (a.want_stats) {
+            for (int j = 0; j < a.f; ++j) unorm += (double)urow[j] * (double)urow[j];
+            unorm = sqrt(unorm);
+        }
         // the user's two lists (lanes n and n+32 of its screen wave), lane-major
         const int2* list0 = a.cand + ((ublk << 6) + n) * (int64_t)a.cap;
         const int2* list1 = a.cand + ((ublk << 6) + n + 32) * (int64_t)a.cap;
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
                     const double key = key64(urow, a.I + (int64_t)item * a.f, a.f);
                     const double err = fabs((double)sv - key);
                     st_abs = fmax(st_abs, err);
-                    const double scale = (us.y > 0.0f ? (double)us.y : (double)us.x) * (double)Ci[q];
+                    const double scale = unorm * (double)Ci[q];
                     if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
                     skey[t * EM + kept] = key;
                     sidx[t * EM + kept] = item;
@@ -277,10 +282,10 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 // Per-user bin of kept candidates in certification (LDS).
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     // lanes per user G and kept pairs per lane: 64 pairs per user for the
-    // float32/bfloat16 screens at K <= 16, 256 for larger K or E4M3 at
-    // K <= 16, 1024 for E4M3 at larger K (its coarse screen keeps hundreds)
+    // float32/bfloat16 screens at K <= 16, 256 at larger K, 1024 for E4M3
+    // (its coarse screen keeps hundreds of pairs per user)
     const bool fp8 = p.prec == PREC_FP8;
-    const int G = (!fp8 && p.K <= 16) ? 8 : ((fp8 && p.K > 16) ? 64 : 16);
+    const int G = (!fp8 && p.K <= 16) ? 8 : (fp8 ? 64 : 16);
     const int64_t threads = p.n_ublk * 32 * G;
     const dim3 grid((unsigned)((threads + 255) / 256)), blk(256);
     if (G == 8)

@@ -105,21 +105,43 @@ __global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ U
     if (on) assign[u] = bi;
 }
 
-// Fixed-point per-cluster sums and counts (order independent).
+// Fixed-point per-cluster sums and counts (order independent).  When the
+// C x f sums fit in LDS a workgroup first aggregates its 256 users there, so
+// each (cluster, factor) receives one global atomic per workgroup.
 __global__ void __launch_bounds__(256) kmeans_sum_kernel(const float* __restrict__ U, int64_t n_u,
                                                          int f, const int* __restrict__ assign,
                                                          const unsigned int* absmax_bits,
                                                          unsigned long long* sums,
                                                          unsigned int* counts, int C) {
+    __shared__ unsigned long long ls[4096];
+    __shared__ unsigned int lc[512];
     const double scale = fixed_scale(n_u, *absmax_bits);
     const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (u >= n_u) return;
-    const int c = assign[u];
-    atomicAdd(&counts[c], 1u);
-    const float* row = U + u * f;
-    for (int j = 0; j < f; ++j) {
-        const long long v = llrint((double)row[j] * scale);
-        atomicAdd(&sums[(int64_t)c * f + j], (unsigned long long)v);
+    const bool local = (int64_t)C * f <= 4096 && C <= 512;
+    if (local) {
+        for (int t = threadIdx.x; t < C * f; t += blockDim.x) ls[t] = 0ull;
+        for (int t = threadIdx.x; t < C; t += blockDim.x) lc[t] = 0u;
+        __syncthreads();
+    }
+    if (u < n_u) {
+        const int c = assign[u];
+        const float* row = U + u * f;
+        if (local) {
+            atomicAdd(&lc[c], 1u);
+            for (int j = 0; j < f; ++j)
+                atomicAdd(&ls[c * f + j], (unsigned long long)llrint((double)row[j] * scale));
+        } else {
+            atomicAdd(&counts[c], 1u);
+            for (int j = 0; j < f; ++j)
+                atomicAdd(&sums[(int64_t)c * f + j], (unsigned long long)llrint((double)row[j] * scale));
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < C * f; t += blockDim.x)
+            if (ls[t]) atomicAdd(&sums[t], ls[t]);
+        for (int t = threadIdx.x; t < C; t += blockDim.x)
+            if (lc[t]) atomicAdd(&counts[t], lc[t]);
     }
 }
 
