@@ -67,6 +67,28 @@ void oracle_user_keys(const float *u, const float *I, int64_t n_i, int32_t f, do
 }
 
 /*
+ * Keys of given pairs: out[r*K + k] = key(U[r], I[idx[r*K + k]]) for rows
+ * r < n_u.  Returns -1 if an index lies outside [0, n_i).
+ */
+int oracle_pair_keys(const float *U, int64_t n_u, const float *I, int64_t n_i, int32_t f,
+                     int32_t K, const int32_t *idx, double *out) {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t r = 0; r < n_u; ++r) {
+        for (int32_t k = 0; k < K; ++k) {
+            const int32_t i = idx[r * K + k];
+            if (i < 0 || i >= n_i) {
+                bad = 1;
+                out[r * K + k] = 0.0;
+                continue;
+            }
+            out[r * K + k] = oracle_key(U + r * (int64_t)f, I + (int64_t)i * f, f);
+        }
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * Top-K for each user.  U is n_u x f, I is n_i x f, both row-major float32.
  * out_idx and out_key are n_u x K.  Returns 0 on success, -1 on bad
  * arguments, -2 on allocation failure.  nthreads <= 0 uses the OpenMP default.

@@ -42,6 +42,9 @@ def _load():
         lib.oracle_key.argtypes = [f32p, f32p, ctypes.c_int32]
         lib.oracle_user_keys.restype = None
         lib.oracle_user_keys.argtypes = [f32p, f32p, ctypes.c_int64, ctypes.c_int32, f64p]
+        lib.oracle_pair_keys.restype = ctypes.c_int
+        lib.oracle_pair_keys.argtypes = [f32p, ctypes.c_int64, f32p, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_int32, i32p, f64p]
         lib.oracle_topk.restype = ctypes.c_int
         lib.oracle_topk.argtypes = [f32p, ctypes.c_int64, f32p, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, i32p, f64p, ctypes.c_int32]
@@ -71,6 +74,21 @@ def user_keys(u, I) -> np.ndarray:
     out = np.empty(I.shape[0], dtype=np.float64)
     _load().oracle_user_keys(up, Ip, I.shape[0], I.shape[1],
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def pair_keys(U, I, idx) -> np.ndarray:
+    """Keys of the pairs (r, idx[r, k]): float64 [n_u, K]."""
+    U, Up = _f32(U)
+    I, Ip = _f32(I)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    assert idx.ndim == 2 and idx.shape[0] == U.shape[0]
+    out = np.empty(idx.shape, dtype=np.float64)
+    rc = _load().oracle_pair_keys(Up, U.shape[0], Ip, I.shape[0], U.shape[1], idx.shape[1],
+                                  idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError("pair_keys: index out of range")
     return out
 
 

@@ -41,3 +41,19 @@ def assert_parity(idx, score, U, I, K, users=None):
     assert bad.size == 0, (f"{bad.size} users differ; first user {bad[0]}: gpu {gi[bad[0]][:12]} "
                            f"oracle {ri[bad[0]][:12]}")
     np.testing.assert_array_equal(gs, rk)
+
+
+def assert_properties_all_users(idx, score, U, I, K):
+    """Checks that hold at any size, on every user: each returned score is
+    the oracle's key of its (user, item) pair, bit for bit; items are
+    distinct and in range; rows are ordered by (key desc, index asc)."""
+    n_u = U.shape[0]
+    assert idx.shape == (n_u, K) and score.shape == (n_u, K)
+    assert idx.min() >= 0 and idx.max() < I.shape[0]
+    np.testing.assert_array_equal(score, oracle_topk.pair_keys(U, I, idx))
+    if K > 1:
+        s = np.sort(idx, axis=1)
+        assert np.all(s[:, 1:] != s[:, :-1]), "duplicate items in a row"
+        d = score[:, :-1] - score[:, 1:]
+        ok = (d > 0) | ((d == 0) & (idx[:, :-1] < idx[:, 1:]))
+        assert np.all(ok), "a row is not ordered by (key desc, index asc)"

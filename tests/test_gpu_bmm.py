@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import mipsgen
-from gpu_util import assert_parity, gpu_topk, log
+from gpu_util import assert_parity, assert_properties_all_users, gpu_topk, log
 
 pytestmark = pytest.mark.gpu
 PRECS = ["fp32", "bf16", "fp8"]
@@ -140,8 +140,32 @@ def test_mf_full_size_sampled(prec, K):
     # hundreds of candidates per user, so more of them take that path.
     limit = U.shape[0] // 10 if (prec == "fp8" and K >= 32) else U.shape[0] // 1000
     assert st["overflow_users"] <= limit
-    # every returned row is sorted by (key desc, index asc) and duplicate-free
-    assert np.all(np.diff(score, axis=1) <= 0)
+    assert_properties_all_users(idx, score, U, I, K)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_precision_workload_full_size(prec):
+    """1,000,000 x 136,000, f = 100, K = 10 (the precision form): every user
+    on the GPU, 300 sampled users against the oracle, the any-size
+    properties on every user."""
+    log(f"precision workload full size prec={prec}")
+    U, I = _precision_full()
+    idx, score, st = gpu_topk(U, I, 10, prec, stats=True)
+    log(f"  stats {st}")
+    users = mipsgen.sample_users(U.shape[0], 300, seed=11)
+    assert_parity(idx, score, U, I, 10, users=users)
+    assert_properties_all_users(idx, score, U, I, 10)
+    assert st["overflow_users"] <= U.shape[0] // 1000
+
+
+_PR = {}
+
+
+def _precision_full():
+    if "x" not in _PR:
+        _MF.clear()
+        _PR["x"] = mipsgen.generate("precision", 0)
+    return _PR["x"]
 
 
 _MF = {}

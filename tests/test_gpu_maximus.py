@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import mipsgen
-from gpu_util import assert_parity, log, to_dev
+from gpu_util import assert_properties_all_users, assert_parity, log, to_dev
 from oracle import maximus as M
 from oracle import topk as oracle_topk
 
@@ -126,6 +126,7 @@ def test_clustered_full_size_matches_oracle_and_bmm(C):
     np.testing.assert_array_equal(score, bmm[1].cpu().numpy())
     users = mipsgen.sample_users(U.shape[0], 1000, seed=C)
     assert_parity(idx, score, U, I, 10, users=users)
+    assert_properties_all_users(idx, score, U, I, 10)
     assert st["mean_items_visited"] < 0.1 * I.shape[0]
     assert st["overflow_users"] <= U.shape[0] // 1000
 

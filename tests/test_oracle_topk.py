@@ -157,3 +157,26 @@ def test_golden_hand_example(oracle_lib):
     idx, key = T.topk(U, I, g["K"])
     np.testing.assert_array_equal(idx, np.array(g["expected_idx"]))
     np.testing.assert_array_equal(key, np.array(g["expected_key"], dtype=np.float64))
+
+
+def test_pair_keys_independent_numpy_and_hand_example(oracle_lib):
+    """pair_keys against the independent left-to-right numpy sum (random
+    pairs) and the hand-worked integer ratings."""
+    U, I = mipsgen.generate("mf", 3, n_users=200, n_items=700, f=50)
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, I.shape[0], size=(U.shape[0], 12)).astype(np.int32)
+    U64 = U.astype(np.float64)
+    I64 = I.astype(np.float64)[idx]            # [n_u, 12, f]
+    acc = np.zeros(idx.shape)
+    for j in range(U.shape[1]):
+        acc = acc + U64[:, None, j] * I64[:, :, j]
+    np.testing.assert_array_equal(T.pair_keys(U, I, idx), acc)
+    with open(os.path.join(GOLDEN, "topk_hand_example.json")) as fh:
+        g = json.load(fh)
+    Ug = np.array(g["U"], dtype=np.float32)
+    Ig = np.array(g["I"], dtype=np.float32)
+    all_idx = np.tile(np.arange(Ig.shape[0], dtype=np.int32), (Ug.shape[0], 1))
+    np.testing.assert_array_equal(T.pair_keys(Ug, Ig, all_idx),
+                                  np.array(g["ratings_by_hand"], dtype=np.float64))
+    with pytest.raises(ValueError):
+        T.pair_keys(Ug, Ig, all_idx + 1)
