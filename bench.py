@@ -143,7 +143,38 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
                        "index_match_sampled": float(np.mean(np.all(idx.cpu().numpy()[users] == ri, 1)))}
         del ix, holder
     mx["bmm_bf16_ms_same_data"] = t_bmm
+    # new users: 10,000 fresh draws of the same mixture against the C=64 index
+    ix = mips.maximus_build(Ut, It, 64, 3, 0, 0)
+    Un, _ = mipsgen.generate("clustered", 1, n_users=10000, n_items=1)
+    (Unt,) = [torch.from_numpy(Un).to(dev)]
+    tn = timed(torch, lambda: ix.query_users(Unt, 10, "bf16"), 5)
+    nidx, nsc, nst = ix.query_users(Unt, 10, "bf16", stats=True)
+    ri, _ = oracle_topk.topk(Un[:200], I, 10)
+    mx["new_users_10000_C64"] = {"query_ms": tn, "mean_items_visited": nst["mean_items_visited"],
+                                 "exact_path_users": nst["overflow_users"],
+                                 "index_match_sampled": float(np.mean(np.all(nidx.cpu().numpy()[:200] == ri, 1)))}
+    del ix
     out["maximus_clustered_480000x17770_f50_K10"] = mx
+    # Optimus (Section IV) on both 480,000 x 17,770 workloads
+    log("extras: optimus")
+    op = {}
+    for wl in ("clustered", "mf"):
+        if wl == "mf":
+            del Ut, It
+            U, I = mipsgen.generate("mf", 0)
+            Ut = torch.from_numpy(U).to(dev)
+            It = torch.from_numpy(I).to(dev)
+        holder = {}
+        def run():
+            holder["r"] = mips.optimus_topk(Ut, It, 10, "bf16", n_clusters=64)
+        t = timed(torch, run, 3)
+        oidx, osc, rep = holder["r"]
+        users = mipsgen.sample_users(U.shape[0], 200, seed=5)
+        ri, _ = oracle_topk.topk(U[users], I, 10)
+        rep["total_ms"] = t
+        rep["index_match_sampled"] = float(np.mean(np.all(oidx.cpu().numpy()[users] == ri, 1)))
+        op[wl] = rep
+    out["optimus_480000x17770_f50_K10"] = op
     del Ut, It, U, I
     torch.cuda.empty_cache()
     # --- precision form: 1,000,000 x 136,000, f = 100, K = 10

@@ -146,6 +146,26 @@ int mips_maximus_query(const mips_maximus_index* index, int32_t K, int32_t preci
                        int32_t* out_idx, double* out_score, void* workspace,
                        size_t workspace_bytes, void* stream, mips_stats* stats);
 
+/* Top-K of arbitrary user vectors against the index's items: new users that
+ * were not clustered, or any subset of the indexed users (the paper's
+ * serving setting, Section III-E, and the user samples of the optimizer,
+ * Section IV-A).  Each row of Uq is assigned to its nearest centroid
+ * (Euclidean, as in the build); when its angle to that centroid is at most
+ * the cluster's theta_b, the bound of Eq. (appx_bound) holds for it and it
+ * walks that cluster's list; otherwise (or for a zero or non-finite row) it
+ * takes the exact float64 path.  Same result contract as mips_bmm_topk.
+ *   Uq         n_q x f float32 (device), f as in the index; 1 <= n_q < 2^31
+ *   out_idx    n_q x K int32, out_score n_q x K float64 (device, written)
+ *   workspace  at least mips_maximus_query_users_workspace_size() bytes,
+ *              256-byte aligned, caller-owned
+ * Read-only on the index. */
+size_t mips_maximus_query_users_workspace_size(const mips_maximus_index* index, int64_t n_q,
+                                               int32_t K, int32_t precision);
+int mips_maximus_query_users(const mips_maximus_index* index, const float* Uq, int64_t n_q,
+                             int32_t K, int32_t precision, int32_t* out_idx, double* out_score,
+                             void* workspace, size_t workspace_bytes, void* stream,
+                             mips_stats* stats);
+
 /* Release the index and its device memory (NULL is ignored). */
 void mips_maximus_free(mips_maximus_index* index);
 
@@ -157,6 +177,43 @@ void mips_maximus_free(mips_maximus_index* index);
 int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, int32_t* f,
                         int64_t* n_u, int64_t* n_i, double* centroids, double* theta_b,
                         int32_t* assign, int32_t* lists, float* bounds, void* stream);
+
+/* ------------------------------------------------------------------------- *
+ * Optimus (paper Section IV): online, sample-based choice between the brute
+ * force and the Maximus index.  Builds the index on all users, times both
+ * methods on a seeded random sample of users, extrapolates each to the whole
+ * batch (the index estimate includes its construction time), finishes the
+ * remaining users with the faster method and reuses the sampled answers.
+ * Both methods are exact: the result is the mips_bmm_topk contract whatever
+ * the choice.
+ *   sample_users  0 = default: max(131072, n_u / 100), at most n_u (a sample
+ *                 below one full wave of screen workgroups under-reports the
+ *                 brute force's throughput); otherwise the sample size
+ *   n_clusters, kmeans_iters, seed  as for mips_maximus_build (seed also draws
+ *                 the sample)
+ *   report        host memory, filled when non-NULL
+ * Allocates its own device memory (freed before returning) and synchronises
+ * `stream` (the timings need it).  Returns MIPS_ERR_NOMEM when device memory
+ * runs out.
+ * ------------------------------------------------------------------------- */
+typedef enum { MIPS_OPTIMUS_BMM = 0, MIPS_OPTIMUS_MAXIMUS = 1 } mips_optimus_choice;
+
+typedef struct {
+    int32_t choice;              /* a mips_optimus_choice                                  */
+    int32_t reserved;
+    int64_t sample_users;        /* users in the sample                                    */
+    double  build_ms;            /* Maximus index construction                             */
+    double  bmm_sample_ms;       /* brute force on the sample                              */
+    double  maximus_sample_ms;   /* Maximus queries on the sample                          */
+    double  est_bmm_ms;          /* brute force extrapolated to all users                  */
+    double  est_maximus_ms;      /* construction + queries extrapolated to all users       */
+    double  finish_ms;           /* the chosen method on the other users, results in place */
+} mips_optimus_report;
+
+int mips_optimus_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f,
+                      int32_t K, int32_t precision, int32_t n_clusters, int32_t kmeans_iters,
+                      uint64_t seed, int64_t sample_users, int32_t* out_idx, double* out_score,
+                      void* stream, mips_optimus_report* report);
 
 /* ------------------------------------------------------------------------- *
  * Backward of a loss on the top-K scores (not in the paper).  With the top-K

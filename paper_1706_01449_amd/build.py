@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmips.so")
 SOURCES = ["api.cpp", "prep.hip", "screen_bf16.hip", "screen_fp32.hip", "screen_fp8.hip",
-           "certify.hip", "backward.hip", "maximus.hip"]
+           "certify.hip", "backward.hip", "maximus.hip", "optimus.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -356,6 +356,7 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
         a.kexp = (const int*)(ws + L.kexp);
         a.Corig = (const float*)(ws + L.Corig);
         a.Gorig = (const float*)(ws + L.Gorig);
+        a.n_ublk = p.n_ublk;
         a.cnt = (int*)(ws + L.cnt);
         a.cand = (int2*)(ws + L.cand);
         {

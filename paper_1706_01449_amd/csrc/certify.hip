@@ -37,11 +37,55 @@ __device__ __forceinline__ double key64(const float* __restrict__ u, const float
     return acc;
 }
 
+// float64 keys of u against up to four item rows (it[q] < 0: skipped), each
+// summed left to right; the loads of all rows of an 8-factor batch are
+// issued together, so one memory latency covers up to 32 FMAs.
+__device__ __forceinline__ void keys4(const float* __restrict__ u, const float* __restrict__ I,
+                                      int f, const int (&it)[4], double (&acc)[4]) {
+    const float* v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = I + (int64_t)(it[q] >= 0 ? it[q] : 0) * f;
+        acc[q] = 0.0;
+    }
+    int j = 0;
+    if ((f & 1) == 0) {
+        const float2* u2 = (const float2*)u;
+        for (; j + 8 <= f; j += 8) {
+            float2 x[4], y[4][4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = u2[(j >> 1) + e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (it[q] < 0) continue;
+                const float2* v2 = (const float2*)v[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[q][e] = v2[(j >> 1) + e];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (it[q] < 0) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc[q] = __fma_rn((double)x[e].x, (double)y[q][e].x, acc[q]);
+                    acc[q] = __fma_rn((double)x[e].y, (double)y[q][e].y, acc[q]);
+                }
+            }
+        }
+    }
+    for (; j < f; ++j) {
+        const double x = (double)u[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (it[q] >= 0) acc[q] = __fma_rn(x, (double)v[q][j], acc[q]);
+    }
+}
+
 // G lanes per user (a group, contiguous in the wave), EM kept pairs per lane.
 // The screen left each user two candidate lists (its two lanes' halves);
-// lane g of the group takes entries g, g+G, ... of their concatenation, keeps
-// those whose upper bound reaches tau_u, rescores them in float64 and writes
-// them to its LDS slots.  The rank of a kept pair among the group's kept
+// lane g of the group takes entries g, g+G, ... of their concatenation,
+// rescores in float64 those whose upper bound reaches tau_u, and writes the
+// ones whose key reaches tau_u to its LDS slots.  The rank of a kept pair among the group's kept
 // pairs by (key desc, index asc) is its output position.  A user goes to the
 // exact fallback when a candidate list overflowed, a lane kept more than EM
 // pairs, or fewer than K pairs were kept.
@@ -74,10 +118,11 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
     bool bad = (c0 > a.cap) || (c1 > a.cap);
     const int m0 = min(c0, a.cap), m1 = min(c1, a.cap);
     const int tot = flagged ? 0 : m0 + m1;
-    int kept = 0;
+    int kept = 0, rescored = 0;
     double st_abs = 0.0, st_rel = 0.0;
     if (!flagged) {
         const float4 us = a.uscal[u];
+        const double tau64 = (double)us.w;
         const float* urow = a.U + u * a.f;
         double unorm = 0.0;   // ||u||, for the relative error statistic only
         if (a.want_stats) {
@@ -102,19 +147,36 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
                 Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
                 Gi[q] = (item >= 0) ? a.Gorig[item] : 0.0f;
             }
+            int it[4];
+            bool anyk = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int item = e[q].y;
-                if (item < 0) continue;
                 const float sv = __int_as_float(e[q].x);
                 const float eb = fmaf(us.x, Ci[q], fmaf(us.y, Gi[q], us.z));
-                if (!(sv + eb >= us.w)) continue;
-                if (kept < EM) {
-                    const double key = key64(urow, a.I + (int64_t)item * a.f, a.f);
+                it[q] = (item >= 0 && sv + eb >= us.w) ? item : -1;
+                anyk = anyk || it[q] >= 0;
+            }
+            if (!anyk) continue;
+            double k4[4];
+            keys4(urow, a.I, a.f, it, k4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int item = it[q];
+                if (item < 0) continue;
+                const float sv = __int_as_float(e[q].x);
+                const double key = k4[q];
+                ++rescored;
+                if (a.want_stats) {
                     const double err = fabs((double)sv - key);
                     st_abs = fmax(st_abs, err);
                     const double scale = unorm * (double)Ci[q];
                     if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+                }
+                // tau_u is at most the K-th largest key, so a pair whose key
+                // is below it is beaten by K items and needs no rank
+                if (key < tau64) continue;
+                if (kept < EM) {
                     skey[t * EM + kept] = key;
                     sidx[t * EM + kept] = item;
                 }
@@ -158,7 +220,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
     // statistics: reduce over the wave, one atomic each
     unsigned long long st_cand = (g == 0 && !flagged) ? (unsigned long long)(c0 + c1) : 0ull;
     unsigned long long st_max = (g == 0 && valid) ? (unsigned long long)(c0 + c1) : 0ull;
-    unsigned long long st_resc = (unsigned long long)(kept < EM ? kept : EM);
+    unsigned long long st_resc = (unsigned long long)rescored;
     for (int off = 32; off >= 1; off >>= 1) {
         st_cand += __shfl_xor(st_cand, off);
         st_resc += __shfl_xor(st_resc, off);
@@ -281,11 +343,11 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 
 // Per-user bin of kept candidates in certification (LDS).
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    // lanes per user G and kept pairs per lane: 64 pairs per user for the
-    // float32/bfloat16 screens at K <= 16, 256 at larger K, 1024 for E4M3
-    // (its coarse screen keeps hundreds of pairs per user)
+    // lanes per user G and LDS slots per lane EM (pairs whose key reaches
+    // tau_u): 64 per user for the float32/bfloat16 screens at K <= 16, 256
+    // for larger K or E4M3 at K <= 16, 1024 for E4M3 at larger K
     const bool fp8 = p.prec == PREC_FP8;
-    const int G = (!fp8 && p.K <= 16) ? 8 : (fp8 ? 64 : 16);
+    const int G = (!fp8 && p.K <= 16) ? 8 : ((fp8 && p.K > 16) ? 64 : 16);
     const int64_t threads = p.n_ublk * 32 * G;
     const dim3 grid((unsigned)((threads + 255) / 256)), blk(256);
     if (G == 8)

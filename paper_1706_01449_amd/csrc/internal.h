@@ -90,6 +90,7 @@ struct ScreenArgs {
     int* uflag;               // n_u: 0 normal, 1 on the fallback list
     int* flist;               // n_u: fallback list
     float4* uscal;            // n_u: (A_u, B_u, slack_u, tau_u)
+    int64_t n_ublk;           // user blocks with candidate storage
     int* cnt;                 // n_ublk * 64 candidate counts
     int2* cand;               // n_ublk * 64 lists of cap candidates (score bits, item index)
     int32_t* out_idx;
@@ -132,6 +133,7 @@ constexpr int kFallbackMaxK = 4096;
 
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_scan4096(unsigned int* hist, hipStream_t s);
 hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s);
 hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_fp32(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);

@@ -370,6 +370,9 @@ struct mips_maximus_index {
     float* I = nullptr;
     double* cent = nullptr;
     double* theta = nullptr;
+    float* cent32 = nullptr;      // float32 centroids and their squared norms (assignment)
+    float* cnorm2 = nullptr;
+    double* cnorm = nullptr;      // float64 centroid norms (angles)
     int* assign = nullptr;
     int* sorted_users = nullptr;
     int* lists = nullptr;
@@ -436,6 +439,70 @@ std::vector<int> forgy(int64_t n_u, int C, uint64_t seed) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Queries for arbitrary user vectors (new users, or any subset).  A vector
+// may use cluster c's list when its angle to the centroid is at most
+// theta_b[c]: the bound of Eq. (appx_bound) only needs theta_uc <= theta_b
+// (Section III-C), so such a vector is covered exactly like a member.  Each
+// vector tries its nearest centroid; the others take the exact path.
+// ---------------------------------------------------------------------------
+__global__ void qcover_kernel(const float* __restrict__ Uq, int64_t n_q, int f,
+                              const int* __restrict__ qassign, const double* __restrict__ cent,
+                              const double* __restrict__ cnorm, const double* __restrict__ theta,
+                              unsigned int* ccount, int* uflag, int* flist, Ctrl* ctrl) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_q) return;
+    const float* row = Uq + q * f;
+    double n2 = 0.0;
+    bool finite = true;
+    for (int j = 0; j < f; ++j) {
+        finite = finite && __builtin_isfinite(row[j]);
+        n2 += (double)row[j] * (double)row[j];
+    }
+    const int c = qassign[q];
+    bool covered = false;
+    if (finite && n2 > 0.0) {
+        if (!(cnorm[c] > 0.0)) {
+            covered = true;                       // theta_b = pi: the bound is ||i||
+        } else {
+            const double th = stable_angle(row, cent + (int64_t)c * f, f, sqrt(n2), cnorm[c]);
+            covered = th <= theta[c];
+        }
+    }
+    if (!finite) atomicOr(&ctrl->nonfinite, 1u);
+    if (covered) {
+        atomicAdd(&ccount[c], 1u);
+    } else {
+        uflag[q] = 1;
+        const unsigned int k = atomicAdd(&ctrl->fb_count, 1u);
+        flist[k] = (int)q;
+    }
+}
+
+__global__ void qscatter_kernel(int64_t n_q, const int* __restrict__ qassign,
+                                const int* __restrict__ uflag, unsigned int* offs, int* sorted) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_q || uflag[q]) return;
+    const unsigned int pos = atomicAdd(&offs[qassign[q]], 1u);
+    sorted[pos] = (int)q;
+}
+
+// tiles per cluster for runs of `span` users
+__global__ void qtile_count_kernel(const unsigned int* ccount, int C, int span, unsigned int* tcount) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    tcount[c] = (ccount[c] + span - 1) / span;
+}
+
+__global__ void qtiles_kernel(const unsigned int* ccount, const unsigned int* cstart,
+                              const unsigned int* toff, int C, int span, int4* tiles) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const unsigned int n = ccount[c];
+    for (unsigned int o = 0, t = 0; o < n; o += span, ++t)
+        tiles[toff[c] + t] = make_int4(c, (int)(cstart[c] + o), (int)min((unsigned int)span, n - o), 0);
+}
 
 extern "C" {
 
@@ -527,6 +594,9 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
                                               (unsigned long long*)ix->theta);
     theta_fix_kernel<<<grid_of(C), 256, 0, s>>>(cnorm, C, ix->theta);
     TRY(hipGetLastError(), "theta_b");
+    ix->cent32 = cent32;
+    ix->cnorm2 = cnorm2;
+    ix->cnorm = cnorm;
 
     // ---- bounds and per-cluster lists --------------------------------------
     {
@@ -595,11 +665,17 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
             ia.kexp = ix->kexp;
             ia.qrow = q;
             ia.ctrl = tctrl + prec;
-            TRY(launch_item_prep(prec, ia, false, s), "item screen copies");
-            cblockmax_kernel<<<grid_of((int64_t)C * ix->n_blk), 256, 0, s>>>(
-                ix->lists, ix->n_i_pad, ix->n_blk, C, ix->Corig[prec], ix->Gorig[prec],
-                ix->cblockmax[prec]);
-            TRY(hipGetLastError(), "tile maxima");
+            if (p.fast) {
+                TRY(launch_item_prep(prec, ia, false, s), "item screen copies");
+                cblockmax_kernel<<<grid_of((int64_t)C * ix->n_blk), 256, 0, s>>>(
+                    ix->lists, ix->n_i_pad, ix->n_blk, C, ix->Corig[prec], ix->Gorig[prec],
+                    ix->cblockmax[prec]);
+                TRY(hipGetLastError(), "tile maxima");
+            } else if (prec == 0) {
+                // no screen for these sizes (every query takes the exact path):
+                // only the finiteness check of I is needed
+                TRY(launch_nonfinite_scan(ix->I, 0, ix->I, n_i * f, tctrl, s), "finite check");
+            }
         }
         Ctrl h[3];
         TRY(hipMemcpyAsync(h, tctrl, sizeof(h), hipMemcpyDeviceToHost, s), "read maxima");
@@ -667,14 +743,137 @@ size_t mips_maximus_query_workspace_size(const mips_maximus_index* ix, int32_t K
     return o;
 }
 
-int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precision, int32_t* out_idx,
-                       double* out_score, void* workspace, size_t workspace_bytes, void* stream,
-                       mips_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// Walk (screen over the cluster lists), certification and the exact
+// fallback for the users named by `tiles` / `sorted_users` (rows of U).
+int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int precision,
+                          const float* U, int64_t n_u, const int4* tiles, const int* sorted_users,
+                          Ctrl* ctrl, int* uflag, int* flist, float4* uscal, int* cnt, int2* cand,
+                          double* fbkeys, int32_t* out_idx, double* out_score, bool want_stats,
+                          hipStream_t s) {
+    hipError_t e;
+    set_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, ix->maxbits[precision][0], ix->maxbits[precision][1],
+                                     ix->maxbits[precision][2]);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "set maxima");
+    ScreenArgs a{};
+    a.U = U;
+    a.I = ix->I;
+    a.n_u = n_u;
+    a.n_i = ix->n_i;
+    a.n_blk = ix->n_blk;
+    a.n_i_pad = ix->n_i_pad;
+    a.f = ix->f;
+    a.f_pad = p.f_pad;
+    a.nch = p.nch;
+    a.K = p.K;
+    a.cap = p.cap;
+    a.kc = p.kc;
+    a.gamma = p.gamma;
+    a.walk = 1;
+    a.warm_rounds = 1;
+    a.shared_blocks = ix->shared_blocks;
+    a.tiles = tiles;
+    a.sorted_users = sorted_users;
+    a.lists = ix->lists;
+    a.lbound = ix->lbound;
+    a.cblockmax = ix->cblockmax[precision];
+    a.qrow = ix->qrow[precision];
+    a.kexp = ix->kexp;
+    a.Corig = ix->Corig[precision];
+    a.Gorig = ix->Gorig[precision];
+    a.want_stats = want_stats;
+    a.ctrl = ctrl;
+    a.uflag = uflag;
+    a.flist = flist;
+    a.uscal = uscal;
+    a.n_ublk = p.n_ublk;
+    a.cnt = cnt;
+    a.cand = cand;
+    a.out_idx = out_idx;
+    a.out_score = out_score;
+    if (p.fast) {
+        if (p.n_waves > 0) {
+            {
+                PhaseTimer t(MIPS_PHASE_WALK, s);
+                if ((e = launch_screen(p, a, s)) != hipSuccess) return hip_fail(e, "walk");
+            }
+            PhaseTimer t(MIPS_PHASE_CERTIFY, s);
+            if ((e = launch_certify(p, a, s)) != hipSuccess) return hip_fail(e, "certify");
+        }
+    } else {
+        if ((e = launch_flag_all(n_u, uflag, flist, ctrl, s)) != hipSuccess) return hip_fail(e, "flag all");
+    }
+    PhaseTimer t(MIPS_PHASE_FALLBACK, s);
+    FallbackArgs fa{};
+    fa.U = U;
+    fa.I = ix->I;
+    fa.n_u = n_u;
+    fa.n_i = ix->n_i;
+    fa.f = ix->f;
+    fa.K = p.K;
+    fa.flist = flist;
+    fa.ctrl = ctrl;
+    fa.keys = fbkeys;
+    fa.out_idx = out_idx;
+    fa.out_score = out_score;
+    if ((e = launch_fallback(p, fa, s)) != hipSuccess) return hip_fail(e, "fallback");
+    return MIPS_OK;
+}
+
+int check_query_args(const mips_maximus_index* ix, int32_t K, int32_t precision, int32_t* out_idx,
+                     double* out_score) {
     if (!ix) return fail(MIPS_ERR_ARG, "index is NULL");
     if (!out_idx || !out_score) return fail(MIPS_ERR_ARG, "null output pointer");
     if (K < 1 || (int64_t)K > ix->n_i) return fail(MIPS_ERR_ARG, "K must be in [1, n_i] (got %d)", K);
     if (K > kFallbackMaxK) return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported", kFallbackMaxK);
     if (precision < 0 || precision > 2) return fail(MIPS_ERR_ARG, "unknown precision %d", precision);
+    return MIPS_OK;
+}
+
+// Workspace of a vector query: sizes in one place for the size function and
+// the query.
+struct QueryLayout {
+    size_t ctrl, uflag, ccount, tcount, tiles, zero_end;
+    size_t flist, uscal, qassign, sorted, cnt, cand, fbkeys, total;
+    int64_t max_tiles;
+};
+
+QueryLayout query_layout(const mips_maximus_index* ix, const ScreenPlan& p, int64_t n_q) {
+    QueryLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += (b + 255) & ~(size_t)255; return r; };
+    const int span = kTile * p.UB;
+    L.max_tiles = p.fast ? (n_q + span - 1) / span + ix->C : 0;
+    const int64_t n_ublk = L.max_tiles * p.UB;
+    L.ctrl = take(sizeof(Ctrl));
+    L.uflag = take((size_t)n_q * 4);
+    L.ccount = take(2 * kBuckets * sizeof(unsigned int));
+    L.tcount = take(2 * kBuckets * sizeof(unsigned int));
+    L.tiles = take((size_t)std::max<int64_t>(L.max_tiles, 1) * sizeof(int4));
+    L.zero_end = o;
+    L.flist = take((size_t)n_q * 4);
+    L.uscal = take((size_t)n_q * 16);
+    L.qassign = take((size_t)n_q * 4);
+    L.sorted = take((size_t)n_q * 4);
+    L.cnt = take((size_t)n_ublk * 64 * 4);
+    L.cand = take((size_t)n_ublk * 64 * p.cap * 8);
+    L.fbkeys = take((size_t)p.fb_grid * ix->n_i * 8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precision, int32_t* out_idx,
+                       double* out_score, void* workspace, size_t workspace_bytes, void* stream,
+                       mips_stats* stats) {
+    int rc = check_query_args(ix, K, precision, out_idx, out_score);
+    if (rc != MIPS_OK) return rc;
     const size_t need = mips_maximus_query_workspace_size(ix, K, precision);
     if (!workspace || workspace_bytes < need)
         return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
@@ -699,75 +898,83 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
     double* fbkeys = (double*)take((size_t)p.fb_grid * ix->n_i * 8);
     hipError_t e;
     if ((e = launch_zero(ws, zero_bytes, s)) != hipSuccess) return hip_fail(e, "zero");
-    set_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, ix->maxbits[precision][0], ix->maxbits[precision][1],
-                                     ix->maxbits[precision][2]);
-    ScreenArgs a{};
-    a.U = ix->U;
-    a.I = ix->I;
-    a.n_u = ix->n_u;
-    a.n_i = ix->n_i;
-    a.n_blk = ix->n_blk;
-    a.n_i_pad = ix->n_i_pad;
-    a.f = ix->f;
-    a.f_pad = p.f_pad;
-    a.nch = p.nch;
-    a.K = K;
-    a.cap = p.cap;
-    a.kc = p.kc;
-    a.gamma = p.gamma;
-    a.walk = 1;
-    a.warm_rounds = 1;
-    a.shared_blocks = ix->shared_blocks;
-    a.tiles = ix->tiles[slot];
-    a.sorted_users = ix->sorted_users;
-    a.lists = ix->lists;
-    a.lbound = ix->lbound;
-    a.cblockmax = ix->cblockmax[precision];
-    a.qrow = ix->qrow[precision];
-    a.kexp = ix->kexp;
-    a.Corig = ix->Corig[precision];
-    a.Gorig = ix->Gorig[precision];
-    a.want_stats = stats != nullptr;
-    a.ctrl = ctrl;
-    a.uflag = uflag;
-    a.flist = flist;
-    a.uscal = uscal;
-    a.cnt = cnt;
-    a.cand = cand;
-    a.out_idx = out_idx;
-    a.out_score = out_score;
-    if (p.fast) {
-        {
-            PhaseTimer t(MIPS_PHASE_WALK, s);
-            if ((e = launch_screen(p, a, s)) != hipSuccess) return hip_fail(e, "walk");
-        }
-        {
-            PhaseTimer t(MIPS_PHASE_CERTIFY, s);
-            if ((e = launch_certify(p, a, s)) != hipSuccess) return hip_fail(e, "certify");
-        }
-    } else {
-        if ((e = launch_flag_all(ix->n_u, uflag, flist, ctrl, s)) != hipSuccess) return hip_fail(e, "flag all");
-    }
-    {
-        PhaseTimer t(MIPS_PHASE_FALLBACK, s);
-        FallbackArgs fa{};
-        fa.U = ix->U;
-        fa.I = ix->I;
-        fa.n_u = ix->n_u;
-        fa.n_i = ix->n_i;
-        fa.f = ix->f;
-        fa.K = K;
-        fa.flist = flist;
-        fa.ctrl = ctrl;
-        fa.keys = fbkeys;
-        fa.out_idx = out_idx;
-        fa.out_score = out_score;
-        if ((e = launch_fallback(p, fa, s)) != hipSuccess) return hip_fail(e, "fallback");
-    }
+    rc = walk_certify_fallback(ix, p, precision, ix->U, ix->n_u, ix->tiles[slot], ix->sorted_users,
+                               ctrl, uflag, flist, uscal, cnt, cand, fbkeys, out_idx, out_score,
+                               stats != nullptr, s);
+    if (rc != MIPS_OK) return rc;
     if (stats) {
-        const int rc = finish_stats(ctrl, s, ix->n_u, ix->n_i, stats);
+        rc = finish_stats(ctrl, s, ix->n_u, ix->n_i, stats);
         if (rc == MIPS_OK && !p.fast) {
             stats->items_scored = ix->n_u * ix->n_i;
+            stats->mean_items_visited = (double)ix->n_i;
+        }
+        return rc;
+    }
+    return MIPS_OK;
+}
+
+size_t mips_maximus_query_users_workspace_size(const mips_maximus_index* ix, int64_t n_q,
+                                               int32_t K, int32_t precision) {
+    if (!ix || n_q < 1 || n_q >= ((int64_t)1 << 31) || K < 1 || (int64_t)K > ix->n_i ||
+        K > kFallbackMaxK || precision < 0 || precision > 2)
+        return 0;
+    ScreenPlan p;
+    make_screen_plan(n_q, ix->n_i, ix->f, K, precision, 0, &p);
+    return query_layout(ix, p, n_q).total;
+}
+
+int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int64_t n_q, int32_t K,
+                             int32_t precision, int32_t* out_idx, double* out_score,
+                             void* workspace, size_t workspace_bytes, void* stream,
+                             mips_stats* stats) {
+    int rc = check_query_args(ix, K, precision, out_idx, out_score);
+    if (rc != MIPS_OK) return rc;
+    if (!Uq) return fail(MIPS_ERR_ARG, "Uq is NULL");
+    if (n_q < 1 || n_q >= ((int64_t)1 << 31)) return fail(MIPS_ERR_ARG, "n_q must be in [1, 2^31)");
+    const size_t need = mips_maximus_query_users_workspace_size(ix, n_q, K, precision);
+    if (!workspace || workspace_bytes < need)
+        return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
+    if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    ScreenPlan p;
+    make_screen_plan(n_q, ix->n_i, ix->f, K, precision, 0, &p);
+    const QueryLayout L = query_layout(ix, p, n_q);
+    p.n_waves = L.max_tiles;
+    p.n_ublk = p.n_waves * p.UB;
+    char* ws = (char*)workspace;
+    Ctrl* ctrl = (Ctrl*)(ws + L.ctrl);
+    int* uflag = (int*)(ws + L.uflag);
+    unsigned int* ccount = (unsigned int*)(ws + L.ccount);   // counts, then starts
+    unsigned int* tcount = (unsigned int*)(ws + L.tcount);   // tile counts, then offsets
+    int4* tiles = (int4*)(ws + L.tiles);
+    int* flist = (int*)(ws + L.flist);
+    float4* uscal = (float4*)(ws + L.uscal);
+    int* qassign = (int*)(ws + L.qassign);
+    int* sorted = (int*)(ws + L.sorted);
+    hipError_t e;
+    if ((e = launch_zero(ws, L.zero_end, s)) != hipSuccess) return hip_fail(e, "zero");
+    if (p.fast) {
+        PhaseTimer t(MIPS_PHASE_WALK, s);
+        const int C = ix->C, f = ix->f, span = kTile * p.UB;
+        const size_t lds_assign = (size_t)64 * f * sizeof(float);
+        assign_kernel<<<grid_of(n_q), 256, lds_assign, s>>>(Uq, n_q, f, ix->cent32, ix->cnorm2, C, qassign);
+        qcover_kernel<<<grid_of(n_q), 256, 0, s>>>(Uq, n_q, f, qassign, ix->cent, ix->cnorm, ix->theta,
+                                                   ccount, uflag, flist, ctrl);
+        if ((e = launch_scan4096(ccount, s)) != hipSuccess) return hip_fail(e, "scan");
+        qtile_count_kernel<<<grid_of(C), 256, 0, s>>>(ccount, C, span, tcount);
+        if ((e = launch_scan4096(tcount, s)) != hipSuccess) return hip_fail(e, "scan");
+        qtiles_kernel<<<grid_of(C), 256, 0, s>>>(ccount, ccount + kBuckets, tcount + kBuckets, C, span, tiles);
+        qscatter_kernel<<<grid_of(n_q), 256, 0, s>>>(n_q, qassign, uflag, ccount + kBuckets, sorted);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "user grouping");
+    }
+    rc = walk_certify_fallback(ix, p, precision, Uq, n_q, tiles, sorted, ctrl, uflag, flist, uscal,
+                               (int*)(ws + L.cnt), (int2*)(ws + L.cand), (double*)(ws + L.fbkeys),
+                               out_idx, out_score, stats != nullptr, s);
+    if (rc != MIPS_OK) return rc;
+    if (stats) {
+        rc = finish_stats(ctrl, s, n_q, ix->n_i, stats);
+        if (rc == MIPS_OK && !p.fast) {
+            stats->items_scored = n_q * ix->n_i;
             stats->mean_items_visited = (double)ix->n_i;
         }
         return rc;

@@ -39,69 +39,117 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One thread per item: float64 norms of the row, its screen copy and the
-// residual, the descending-norm bucket, and the global maxima.
+// Sixteen lanes per item (lane q takes factors q, q+16, ...; f_pad <= 128):
+// float64 norms of the row, of its screen copy and of the residual, the
+// descending-norm bucket, and the global maxima (reduced over the wave, one
+// atomic per wave).  The order of the float64 partial sums only moves the
+// last bits; every norm is rounded up and the per-user slack covers the rest.
+constexpr int kPrepLanes = 16;
+constexpr int kPrepPer = 128 / kPrepLanes;      // factors per lane at f_pad = 128
+
 template <int PREC>
-__global__ void item_stats_kernel(ItemPrepArgs a) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.n_i) return;
-    const float* row = a.I + i * a.f;
-    double s2 = 0.0;
-    float amax = 0.0f;
-    bool finite = true;
-    for (int j = 0; j < a.f; ++j) {
-        float x = row[j];
-        finite = finite && __builtin_isfinite(x);
-        s2 += (double)x * (double)x;
-        amax = fmaxf(amax, fabsf(x));
-    }
-    int k = 0;
-    if (PREC == PREC_FP8) k = e4m3_row_scale_exp(amax);
-    double r2 = 0.0, q2 = 0.0;
-    if (PREC == PREC_FP32) {
-        float* q = (float*)a.qrow + i * a.f_pad;
-        for (int j = 0; j < a.f_pad; ++j) q[j] = (j < a.f) ? row[j] : 0.0f;
-        q2 = s2;
-    } else if (PREC == PREC_BF16) {
-        uint16_t* q = (uint16_t*)a.qrow + i * a.f_pad;
-        for (int j = 0; j < a.f_pad; ++j) {
-            float x = (j < a.f) ? row[j] : 0.0f;
-            uint16_t hb = f32_to_bf16_bits(x);
-            double d = (double)bf16_bits_to_f32(hb);
-            r2 += ((double)x - d) * ((double)x - d);
-            q2 += d * d;
-            q[j] = hb;
+__global__ void __launch_bounds__(256) item_stats_kernel(ItemPrepArgs a) {
+    __shared__ unsigned int smax[3][4];
+    const int q = threadIdx.x & (kPrepLanes - 1);
+    // the global maxima are reduced over the whole workgroup (one atomic per
+    // workgroup: same-address atomics serialise)
+    unsigned int cb = 0u, eb = 0u, gb = 0u;
+    for (int64_t base = (int64_t)blockIdx.x * (256 / kPrepLanes); base < a.n_i;
+         base += (int64_t)gridDim.x * (256 / kPrepLanes)) {
+        const int64_t i = base + threadIdx.x / kPrepLanes;
+        const bool on = i < a.n_i;
+        const float* row = a.I + (on ? i : 0) * a.f;
+        float x[kPrepPer];
+        double s2 = 0.0;
+        float amax = 0.0f;
+        bool finite = true;
+#pragma unroll
+        for (int e = 0; e < kPrepPer; ++e) {
+            const int j = q + e * kPrepLanes;
+            x[e] = (on && j < a.f) ? row[j] : 0.0f;
+            finite = finite && __builtin_isfinite(x[e]);
+            s2 += (double)x[e] * (double)x[e];
+            amax = fmaxf(amax, fabsf(x[e]));
         }
-    } else {
-        uint8_t* q = (uint8_t*)a.qrow + i * a.f_pad;
-        for (int j = 0; j < a.f_pad; ++j) {
-            float x = (j < a.f) ? row[j] : 0.0f;
-            uint32_t e = e4m3_encode(__builtin_ldexpf(x, -k));
-            double d = __builtin_ldexp((double)e4m3_decode(e), k);
-            r2 += ((double)x - d) * ((double)x - d);
-            q2 += d * d;
-            q[j] = (uint8_t)e;
+        for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
+            s2 += __shfl_xor(s2, off, kPrepLanes);
+            amax = fmaxf(amax, __shfl_xor(amax, off, kPrepLanes));
+            // every lane must take part in the exchange (no short-circuit)
+            const int fp = __shfl_xor((int)finite, off, kPrepLanes);
+            finite = finite && (fp != 0);
         }
-        a.kexp[i] = k;
+        int k = 0;
+        if (PREC == PREC_FP8) k = e4m3_row_scale_exp(amax);
+        double r2 = 0.0, q2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < kPrepPer; ++e) {
+            const int j = q + e * kPrepLanes;
+            if (!on || j >= a.f_pad) continue;
+            if (PREC == PREC_FP32) {
+                ((float*)a.qrow)[i * a.f_pad + j] = x[e];
+            } else if (PREC == PREC_BF16) {
+                const uint16_t hb = f32_to_bf16_bits(x[e]);
+                const double d = (double)bf16_bits_to_f32(hb);
+                r2 += ((double)x[e] - d) * ((double)x[e] - d);
+                q2 += d * d;
+                ((uint16_t*)a.qrow)[i * a.f_pad + j] = hb;
+            } else {
+                const uint32_t b = e4m3_encode(__builtin_ldexpf(x[e], -k));
+                const double d = __builtin_ldexp((double)e4m3_decode(b), k);
+                r2 += ((double)x[e] - d) * ((double)x[e] - d);
+                q2 += d * d;
+                ((uint8_t*)a.qrow)[i * a.f_pad + j] = (uint8_t)b;
+            }
+        }
+        if (PREC == PREC_FP32) {
+            q2 = s2;
+        } else {
+            for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
+                r2 += __shfl_xor(r2, off, kPrepLanes);
+                q2 += __shfl_xor(q2, off, kPrepLanes);
+            }
+        }
+        float C = norm_up_f32(sqrt(s2));
+        float E = norm_up_f32(sqrt(q2));
+        float G = (PREC == PREC_FP32) ? 0.0f : norm_up_f32(sqrt(r2) + (double)a.gamma * sqrt(q2));
+        if (!finite || !on) { C = 0.0f; E = 0.0f; G = 0.0f; }
+        if (on && q == 0) {
+            if (PREC == PREC_FP8) a.kexp[i] = k;
+            a.Corig[i] = C;
+            a.Gorig[i] = G;
+            a.Eorig[i] = E;
+            if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
+            if (a.bucket) {
+                // descending ||i||: 16 buckets per octave from the float bits
+                int bk = (kBuckets - 1) - (int)(__float_as_uint(C) >> 19);
+                bk = bk < 0 ? 0 : (bk >= kBuckets ? kBuckets - 1 : bk);
+                a.bucket[i] = bk;
+            }
+        }
+        // all values are >= 0, so their bit patterns order as integers
+        cb = max(cb, __float_as_uint(C));
+        eb = max(eb, __float_as_uint(E));
+        gb = max(gb, __float_as_uint(G));
     }
-    if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
-    float C = norm_up_f32(sqrt(s2));
-    float E = norm_up_f32(sqrt(q2));
-    float G = (PREC == PREC_FP32) ? 0.0f
-                                  : norm_up_f32(sqrt(r2) + (double)a.gamma * sqrt(q2));
-    if (!finite) { C = 0.0f; E = 0.0f; G = 0.0f; }
-    a.Corig[i] = C;
-    a.Gorig[i] = G;
-    a.Eorig[i] = E;
-    atomicMax(&a.ctrl->cmax_bits, __float_as_uint(C));
-    atomicMax(&a.ctrl->emax_bits, __float_as_uint(E));
-    atomicMax(&a.ctrl->gmax_bits, __float_as_uint(G));
-    if (a.bucket) {
-        // descending ||i||: 16 buckets per octave from the float bits
-        int bk = (kBuckets - 1) - (int)(__float_as_uint(C) >> 19);
-        bk = bk < 0 ? 0 : (bk >= kBuckets ? kBuckets - 1 : bk);
-        a.bucket[i] = bk;
-        atomicAdd(&a.hist[bk], 1u);
+    for (int off = 32; off >= 1; off >>= 1) {
+        cb = max(cb, (unsigned int)__shfl_xor((int)cb, off));
+        eb = max(eb, (unsigned int)__shfl_xor((int)eb, off));
+        gb = max(gb, (unsigned int)__shfl_xor((int)gb, off));
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smax[0][wv] = cb;
+        smax[1][wv] = eb;
+        smax[2][wv] = gb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int m[3];
+        for (int v = 0; v < 3; ++v)
+            m[v] = max(max(smax[v][0], smax[v][1]), max(smax[v][2], smax[v][3]));
+        atomicMax(&a.ctrl->cmax_bits, m[0]);
+        atomicMax(&a.ctrl->emax_bits, m[1]);
+        atomicMax(&a.ctrl->gmax_bits, m[2]);
     }
 }
 
@@ -124,11 +172,36 @@ __global__ void __launch_bounds__(1024) bucket_scan_kernel(unsigned int* hist) {
     for (int q = 0; q < 4; ++q) { hist[kBuckets + t * 4 + q] = run; run += v[q]; }
 }
 
-__global__ void bucket_scatter_kernel(ItemPrepArgs a) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.n_i) return;
-    unsigned int pos = atomicAdd(&a.hist[kBuckets + a.bucket[i]], 1u);
-    a.perm[pos] = (int)i;
+// Bucket counts: each workgroup counts its 256 items in LDS and adds the
+// non-zero counts to the global histogram (one atomic per bucket and
+// workgroup instead of one per item on a few hot buckets).
+__global__ void __launch_bounds__(256) bucket_count_kernel(ItemPrepArgs a) {
+    __shared__ unsigned int lh[kBuckets];
+    for (int t = threadIdx.x; t < kBuckets; t += blockDim.x) lh[t] = 0u;
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < a.n_i) atomicAdd(&lh[a.bucket[i]], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kBuckets; t += blockDim.x)
+        if (lh[t]) atomicAdd(&a.hist[t], lh[t]);
+}
+
+// Scatter into bucket order: ranks within the workgroup from LDS atomics,
+// one global atomic per bucket and workgroup reserves the range.  The order
+// inside a bucket is arbitrary (it changes speed only).
+__global__ void __launch_bounds__(256) bucket_scatter_kernel(ItemPrepArgs a) {
+    __shared__ unsigned int lh[kBuckets];
+    for (int t = threadIdx.x; t < kBuckets; t += blockDim.x) lh[t] = 0u;
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int bk = i < a.n_i ? a.bucket[i] : 0;
+    unsigned int local = 0;
+    if (i < a.n_i) local = atomicAdd(&lh[bk], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kBuckets; t += blockDim.x)
+        if (lh[t]) lh[t] = atomicAdd(&a.hist[kBuckets + t], lh[t]);
+    __syncthreads();
+    if (i < a.n_i) a.perm[lh[bk] + local] = (int)i;
 }
 
 // One 64-thread workgroup per item tile: copy the 32 items' screen rows into
@@ -193,6 +266,12 @@ __global__ void nonfinite_scan_kernel(const float* U, int64_t nu, const float* I
     if (bad) atomicOr(&ctrl->nonfinite, 1u);
 }
 
+// Exclusive scan of 4096 counts at hist[0..4096) into hist[4096..8192).
+hipError_t launch_scan4096(unsigned int* hist, hipStream_t s) {
+    bucket_scan_kernel<<<1, 1024, 0, s>>>(hist);
+    return hipGetLastError();
+}
+
 hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
                                  int64_t ni_elems, Ctrl* ctrl, hipStream_t s) {
     nonfinite_scan_kernel<<<dim3(1024), dim3(256), 0, s>>>(U, nu_elems, I, ni_elems, ctrl);
@@ -201,13 +280,19 @@ hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* 
 
 hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s) {
     const unsigned nb = (unsigned)((a.n_i + 255) / 256);
+    if (a.f_pad > 128 || a.f > a.f_pad) return hipErrorInvalidValue;
+    // at most 256 workgroups, each striding over the items 16 at a time
+    const int64_t groups = (a.n_i + 256 / kPrepLanes - 1) / (256 / kPrepLanes);
+    const unsigned ns = (unsigned)(groups < 256 ? groups : 256);
     switch (prec) {
-        case PREC_FP32: item_stats_kernel<PREC_FP32><<<nb, 256, 0, s>>>(a); break;
-        case PREC_BF16: item_stats_kernel<PREC_BF16><<<nb, 256, 0, s>>>(a); break;
-        default: item_stats_kernel<PREC_FP8><<<nb, 256, 0, s>>>(a); break;
+        case PREC_FP32: item_stats_kernel<PREC_FP32><<<ns, 256, 0, s>>>(a); break;
+        case PREC_BF16: item_stats_kernel<PREC_BF16><<<ns, 256, 0, s>>>(a); break;
+        default: item_stats_kernel<PREC_FP8><<<ns, 256, 0, s>>>(a); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !pack) return e;
+    bucket_count_kernel<<<nb, 256, 0, s>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     bucket_scan_kernel<<<1, 1024, 0, s>>>(a.hist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     bucket_scatter_kernel<<<nb, 256, 0, s>>>(a);

@@ -395,23 +395,33 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         for (int ub = 0; ub < UB; ++ub) {
             const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
             const float thr = tauf[ub] - ee;
-            float m = acc[ub][0];
+            // maxima of the four row groups {4g .. 4g+3}, then of the tile
+            float gm4[4];
 #pragma unroll
-            for (int r = 1; r < 16; ++r) m = fmaxf(m, acc[ub][r]);
+            for (int g = 0; g < 4; ++g)
+                gm4[g] = fmaxf(fmaxf(acc[ub][4 * g], acc[ub][4 * g + 1]),
+                               fmaxf(acc[ub][4 * g + 2], acc[ub][4 * g + 3]));
+            const float m = fmaxf(fmaxf(gm4[0], gm4[1]), fmaxf(gm4[2], gm4[3]));
             if (ballot(m >= thr)) {
+                // a group is walked only when some lane's group maximum passes
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float v = acc[ub][r];
-                    const bool hit = (v >= thr) && (v > ninf);
-                    if (ballot(hit)) {
-                        // item index of output row 8g + 4h + q, held by lane (row)
-                        const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-                        const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
-                        if (hit) {
-                            list_insert(lst[ub], v - ee);
-                            if (cnt[ub] < a.cap)
-                                cptr[ub][cnt[ub]] = make_int2(__float_as_int(v), orig);
-                            cnt[ub] += 1;
+                for (int g = 0; g < 4; ++g) {
+                    if (!ballot(gm4[g] >= thr)) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = 4 * g + q;
+                        const float v = acc[ub][r];
+                        const bool hit = (v >= thr) && (v > ninf);
+                        if (ballot(hit)) {
+                            // item index of output row 8g + 4h + q, held by lane (row)
+                            const int row = 8 * g + 4 * h + q;
+                            const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
+                            if (hit) {
+                                list_insert(lst[ub], v - ee);
+                                if (cnt[ub] < a.cap)
+                                    cptr[ub][cnt[ub]] = make_int2(__float_as_int(v), orig);
+                                cnt[ub] += 1;
+                            }
                         }
                     }
                 }
@@ -477,7 +487,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
         const int64_t ublk = w * UB + ub;
-        a.cnt[(ublk << 6) + lane] = cnt[ub];
+        if (ublk < a.n_ublk) a.cnt[(ublk << 6) + lane] = cnt[ub];
         bool valid;
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
         if (valid && h == 0) {

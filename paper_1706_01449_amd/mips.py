@@ -42,6 +42,25 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class OptimusReport(ctypes.Structure):
+    _fields_ = [
+        ("choice", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("sample_users", ctypes.c_int64),
+        ("build_ms", ctypes.c_double),
+        ("bmm_sample_ms", ctypes.c_double),
+        ("maximus_sample_ms", ctypes.c_double),
+        ("est_bmm_ms", ctypes.c_double),
+        ("est_maximus_ms", ctypes.c_double),
+        ("finish_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["choice"] = "maximus" if self.choice == 1 else "bmm"
+        return d
+
+
 def lib_path() -> str:
     return _LIB_PATH
 
@@ -78,6 +97,14 @@ def lib():
     L.mips_maximus_query_workspace_size.argtypes = [vp, c_i32, c_i32]
     L.mips_maximus_query.restype = ctypes.c_int
     L.mips_maximus_query.argtypes = [vp, c_i32, c_i32, vp, vp, vp, c_sz, vp, ctypes.POINTER(Stats)]
+    L.mips_maximus_query_users_workspace_size.restype = c_sz
+    L.mips_maximus_query_users_workspace_size.argtypes = [vp, c_i64, c_i32, c_i32]
+    L.mips_maximus_query_users.restype = ctypes.c_int
+    L.mips_maximus_query_users.argtypes = [vp, vp, c_i64, c_i32, c_i32, vp, vp, vp, c_sz, vp,
+                                           ctypes.POINTER(Stats)]
+    L.mips_optimus_topk.restype = ctypes.c_int
+    L.mips_optimus_topk.argtypes = [vp, c_i64, vp, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_u64,
+                                    c_i64, vp, vp, vp, ctypes.POINTER(OptimusReport)]
     L.mips_maximus_free.restype = None
     L.mips_maximus_free.argtypes = [vp]
     L.mips_maximus_export.restype = ctypes.c_int
@@ -197,6 +224,33 @@ class MaximusIndex:
             return idx, score, st.as_dict()
         return idx, score
 
+    def query_users(self, Uq: torch.Tensor, K: int, precision="bf16", stats: bool = False,
+                    workspace: torch.Tensor | None = None):
+        """Top-K of arbitrary user vectors (new users or any subset) against
+        the index's items."""
+        L = lib()
+        p = _prec(precision)
+        Uq = _mat(Uq, "Uq")
+        if Uq.shape[1] != self.f:
+            raise MipsError(-1, f"Uq has {Uq.shape[1]} factors, the index {self.f}")
+        n_q = Uq.shape[0]
+        need = L.mips_maximus_query_users_workspace_size(self._h, n_q, int(K), p)
+        if need == 0:
+            raise MipsError(-1, "invalid query sizes")
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        idx = torch.empty((n_q, K), dtype=torch.int32, device=self.device)
+        score = torch.empty((n_q, K), dtype=torch.float64, device=self.device)
+        st = Stats() if stats else None
+        rc = L.mips_maximus_query_users(self._h, Uq.data_ptr(), n_q, int(K), p, idx.data_ptr(),
+                                        score.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                        _stream(self.device),
+                                        ctypes.byref(st) if st is not None else None)
+        _check(rc)
+        if stats:
+            return idx, score, st.as_dict()
+        return idx, score
+
     def export(self):
         """Host copies of the index: centroids, theta_b, assignment, lists, bounds."""
         import numpy as np
@@ -235,6 +289,25 @@ def maximus_build(U: torch.Tensor, I: torch.Tensor, n_clusters: int = 8, kmeans_
                               _stream(U.device), ctypes.byref(h))
     _check(rc)
     return MaximusIndex(h.value, U.device, U.shape[0], I.shape[0], U.shape[1])
+
+
+def optimus_topk(U: torch.Tensor, I: torch.Tensor, K: int, precision="bf16", n_clusters: int = 64,
+                 kmeans_iters: int = 3, seed: int = 0, sample_users: int = 0):
+    """Exact top-K of every user with the method Optimus picks online (paper
+    Section IV).  Returns (idx, score, report dict)."""
+    U = _mat(U, "U")
+    I = _mat(I, "I")
+    if U.shape[1] != I.shape[1]:
+        raise ValueError("U and I must have the same number of columns")
+    n_u, f = U.shape
+    idx = torch.empty((n_u, K), dtype=torch.int32, device=U.device)
+    score = torch.empty((n_u, K), dtype=torch.float64, device=U.device)
+    rep = OptimusReport()
+    _check(lib().mips_optimus_topk(U.data_ptr(), n_u, I.data_ptr(), I.shape[0], f, int(K),
+                                   _prec(precision), int(n_clusters), int(kmeans_iters), int(seed),
+                                   int(sample_users), idx.data_ptr(), score.data_ptr(),
+                                   _stream(U.device), ctypes.byref(rep)))
+    return idx, score, rep.as_dict()
 
 
 def topk_backward(U: torch.Tensor, I: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor):
