@@ -133,6 +133,12 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
         tb = timed(torch, build, 3)
         ix = holder["ix"]
         tq = timed(torch, lambda: ix.query(10, "bf16"), 5)
+        mips.profile_read()
+        mips.profile_enable(True)
+        ix.query(10, "bf16")
+        torch.cuda.synchronize()
+        mips.profile_enable(False)
+        qph = {k: v[0] / max(1, v[1]) for k, v in mips.profile_read().items() if v[1]}
         idx, score, st = ix.query(10, "bf16", stats=True)
         users = mipsgen.sample_users(U.shape[0], 200, seed=C)
         ri, _ = oracle_topk.topk(U[users], I, 10)
@@ -140,12 +146,14 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
                        "users_per_s_query": U.shape[0] / (tq * 1e-3),
                        "users_per_s_end_to_end": U.shape[0] / ((tb + tq) * 1e-3),
                        "mean_items_visited": st["mean_items_visited"],
+                       "exact_path_users": st["overflow_users"], "query_phases_ms": qph,
                        "index_match_sampled": float(np.mean(np.all(idx.cpu().numpy()[users] == ri, 1)))}
         del ix, holder
     mx["bmm_bf16_ms_same_data"] = t_bmm
     # new users: 10,000 fresh draws of the same mixture against the C=64 index
     ix = mips.maximus_build(Ut, It, 64, 3, 0, 0)
-    Un, _ = mipsgen.generate("clustered", 1, n_users=10000, n_items=1)
+    # same seed, more users: the same mixture components, fresh draws
+    Un = mipsgen.generate("clustered", 0, n_users=U.shape[0] + 10000)[0][U.shape[0]:]
     (Unt,) = [torch.from_numpy(Un).to(dev)]
     tn = timed(torch, lambda: ix.query_users(Unt, 10, "bf16"), 5)
     nidx, nsc, nst = ix.query_users(Unt, 10, "bf16", stats=True)
@@ -175,6 +183,19 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
         rep["index_match_sampled"] = float(np.mean(np.all(oidx.cpu().numpy()[users] == ri, 1)))
         op[wl] = rep
     out["optimus_480000x17770_f50_K10"] = op
+    # norm-pruned brute force (stop test with theta_b = pi) on the MF workload
+    ws = torch.empty(mips.lib().mips_bmm_topk_workspace_size(U.shape[0], I.shape[0], U.shape[1], 10,
+                                                              mips.PRECISIONS["bf16"]),
+                     dtype=torch.uint8, device=dev)
+    tp = timed(torch, lambda: mips.norm_pruned_topk(Ut, It, 10, "bf16", workspace=ws), 5)
+    pidx, psc, pst = mips.norm_pruned_topk(Ut, It, 10, "bf16", stats=True, workspace=ws)
+    users = mipsgen.sample_users(U.shape[0], 200, seed=6)
+    ri, _ = oracle_topk.topk(U[users], I, 10)
+    out["norm_pruned_mf_480000x17770_f50_K10"] = {
+        "ms": tp, "users_per_s": U.shape[0] / (tp * 1e-3),
+        "mean_items_visited": pst["mean_items_visited"],
+        "index_match_sampled": float(np.mean(np.all(pidx.cpu().numpy()[users] == ri, 1)))}
+    del ws
     del Ut, It, U, I
     torch.cuda.empty_cache()
     # --- precision form: 1,000,000 x 136,000, f = 100, K = 10

@@ -2,7 +2,7 @@
  * mips.h -- C ABI of libmips: exact batch top-K maximum inner product search
  * on one AMD Instinct MI355X (gfx950).
  *
- * The problem (paper Section II-A, "Problem Statement: Batch Exact MIPS"):
+ * The problem (paper Section II-B, "Problem Statement: Batch Exact MIPS"):
  * given user vectors U (n_u x f) and item vectors I (n_i x f), return for
  * every user the K items with the largest inner product u.i.
  *
@@ -86,7 +86,7 @@ typedef struct {
 
 /* ------------------------------------------------------------------------- *
  * Brute force: blocked matrix multiply fused with a per-user streaming top-K
- * (paper Section II-B, "Blocked Matrix Multiply").  The score matrix U I^T is
+ * (paper Section II-C, "Blocked Matrix Multiply").  The score matrix U I^T is
  * produced tile by tile on the matrix cores and never written to memory.
  * ------------------------------------------------------------------------- */
 
@@ -108,6 +108,21 @@ size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t
 int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
                   int32_t precision, int32_t* out_idx, double* out_score,
                   void* workspace, size_t workspace_bytes, void* stream, mips_stats* stats);
+
+/* Norm-pruned brute force: mips_bmm_topk with early termination.  The items
+ * are already scored in descending-norm tile order; after each tile a user
+ * stops once ||u|| times the largest ||i|| of all later tiles (plus the
+ * rounding slack) is below its K-th best lower bound tau_u, since every later
+ * item then has key < tau_u <= the K-th largest key.  This is the stop test
+ * of Algorithm 1 (Section III-C) with theta_b = pi, i.e. the bound ||i|| of
+ * Eq. (appx_bound) for a cluster with no angular information, and the
+ * length-based pruning the paper discusses for existing indexes
+ * (Section II-D).  Same arguments, workspace size
+ * (mips_bmm_topk_workspace_size) and result as mips_bmm_topk;
+ * stats->mean_items_visited reports the items scored per user. */
+int mips_norm_pruned_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f,
+                          int32_t K, int32_t precision, int32_t* out_idx, double* out_score,
+                          void* workspace, size_t workspace_bytes, void* stream, mips_stats* stats);
 
 /* ------------------------------------------------------------------------- *
  * Maximus (paper Section III, Algorithm 1): k-means over users
@@ -184,6 +199,8 @@ int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, in
  * methods on a seeded random sample of users, extrapolates each to the whole
  * batch (the index estimate includes its construction time), finishes the
  * remaining users with the faster method and reuses the sampled answers.
+ * The sample is systematic: users floor((k + phase) n_u / s), k < s, with a
+ * seeded random phase (evenly spread over the user order).
  * Both methods are exact: the result is the mips_bmm_topk contract whatever
  * the choice.
  *   sample_users  0 = default: max(131072, n_u / 100), at most n_u (a sample
@@ -192,8 +209,8 @@ int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, in
  *   n_clusters, kmeans_iters, seed  as for mips_maximus_build (seed also draws
  *                 the sample)
  *   report        host memory, filled when non-NULL
- * Allocates its own device memory (freed before returning) and synchronises
- * `stream` (the timings need it).  Returns MIPS_ERR_NOMEM when device memory
+ * Allocates its own device memory (stream-ordered, released before
+ * returning) and synchronises `stream` (the timings need it).  Returns MIPS_ERR_NOMEM when device memory
  * runs out.
  * ------------------------------------------------------------------------- */
 typedef enum { MIPS_OPTIMUS_BMM = 0, MIPS_OPTIMUS_MAXIMUS = 1 } mips_optimus_choice;

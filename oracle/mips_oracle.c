@@ -5,7 +5,7 @@
  * loads this file; only the tests, the smoke check and the benchmark's CPU
  * baseline leg do.
  *
- * What it computes (Section II-A, problem statement; Section II-B, brute
+ * What it computes (Section II-B, problem statement; Section II-C, brute
  * force): for every user vector u and every item vector i the rating u.i,
  * then the K items with the largest ratings.  The paper evaluates in double
  * precision but does not fix a summation order or a tie rule, so this oracle

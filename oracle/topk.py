@@ -1,6 +1,6 @@
 """ctypes front end of the C oracle (``mips_oracle.c``).  TEST INFRASTRUCTURE ONLY.
 
-Result definition (Section II-A problem statement, Section II-B brute force):
+Result definition (Section II-B problem statement, Section II-C brute force):
 for each user the K items with the largest inner product, with the keys summed
 in float64 left to right over the factors and ties broken by the lower item
 index.

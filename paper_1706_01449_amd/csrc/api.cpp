@@ -131,7 +131,8 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
 
 struct BmmLayout {
     size_t ctrl, hist, uflag, zero_end;
-    size_t flist, uscal, bucket, perm, Corig, Gorig, Eorig, kexp, qrow, packed, pscale, blockmax;
+    size_t flist, uscal, bucket, perm, Corig, Gorig, Eorig, kexp, qrow, packed, pscale, blockmax,
+        tailmax;
     size_t cnt, cand, fbkeys, total;
 };
 
@@ -157,6 +158,7 @@ static BmmLayout bmm_layout(const ScreenPlan& p) {
         L.packed = take((size_t)p.n_i_pad * p.f_pad * esz);
         L.pscale = take((size_t)p.n_i_pad * 4);
         L.blockmax = take((size_t)p.n_blk * 8);
+        L.tailmax = take((size_t)p.n_blk * 4);
         L.cnt = take((size_t)p.n_ublk * 64 * 4);
         L.cand = take((size_t)p.n_ublk * p.cap * 64 * 8);
     }
@@ -277,9 +279,12 @@ size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t
     return bmm_layout(p).total;
 }
 
-int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
-                  int32_t precision, int32_t* out_idx, double* out_score, void* workspace,
-                  size_t workspace_bytes, void* stream, mips_stats* stats) {
+}  // extern "C"
+
+// Brute force (prune = 0) or norm-pruned brute force (prune = 1).
+static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
+                    int32_t precision, int32_t* out_idx, double* out_score, void* workspace,
+                    size_t workspace_bytes, void* stream, mips_stats* stats, int prune) {
     int rc = check_common(n_u, n_i, f, K, precision);
     if (rc != MIPS_OK) return rc;
     if (!U || !I || !out_idx || !out_score) return fail(MIPS_ERR_ARG, "null array pointer");
@@ -320,6 +325,9 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
             ia.ctrl = ctrl;
             if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
                 return hip_fail(e, "item preparation");
+            if (prune &&
+                (e = launch_tailmax(ia.blockmax, p.n_blk, (float*)(ws + L.tailmax), s)) != hipSuccess)
+                return hip_fail(e, "tile norm maxima");
         } else {
             if ((e = launch_nonfinite_scan(U, n_u * f, I, n_i * f, ctrl, s)) != hipSuccess)
                 return hip_fail(e, "finite check");
@@ -351,6 +359,8 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
         a.packed = ws + L.packed;
         a.pscale = (const int*)(ws + L.pscale);
         a.blockmax = (const float2*)(ws + L.blockmax);
+        a.tailmax = (const float*)(ws + L.tailmax);
+        a.prune = prune;
         a.perm = (const int*)(ws + L.perm);
         a.qrow = ws + L.qrow;
         a.kexp = (const int*)(ws + L.kexp);
@@ -393,6 +403,22 @@ int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int3
         return rc;
     }
     return MIPS_OK;
+}
+
+extern "C" {
+
+int mips_bmm_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f, int32_t K,
+                  int32_t precision, int32_t* out_idx, double* out_score, void* workspace,
+                  size_t workspace_bytes, void* stream, mips_stats* stats) {
+    return bmm_impl(U, n_u, I, n_i, f, K, precision, out_idx, out_score, workspace,
+                    workspace_bytes, stream, stats, 0);
+}
+
+int mips_norm_pruned_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f,
+                          int32_t K, int32_t precision, int32_t* out_idx, double* out_score,
+                          void* workspace, size_t workspace_bytes, void* stream, mips_stats* stats) {
+    return bmm_impl(U, n_u, I, n_i, f, K, precision, out_idx, out_score, workspace,
+                    workspace_bytes, stream, stats, 1);
 }
 
 }  // extern "C"

@@ -1,5 +1,7 @@
 // Certification of the screen's candidates with a float64 rescore, the exact
 // float64 fallback, and the screen launch dispatcher.
+#include <algorithm>
+
 #include "screen_core.h"
 
 namespace mips {
@@ -248,10 +250,81 @@ __device__ __forceinline__ unsigned long long ordered(double k) {
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// Keys of one user against all items, 256 items per step: the items' rows
+// are staged through LDS 32 factors at a time with coalesced loads, then
+// each thread continues its item's left-to-right float64 sum.
+constexpr int kFbRows = 256, kFbCols = 32;
+
+__device__ __forceinline__ void fallback_keys(const FallbackArgs& a, const float* su,
+                                              float (*srow)[kFbCols + 1], double* keys) {
+    const int tid = threadIdx.x;
+    const int f = a.f;
+    for (int64_t base = 0; base < a.n_i; base += kFbRows) {
+        const int nr = (int)min((int64_t)kFbRows, a.n_i - base);
+        const float* src = a.I + base * f;
+        double acc = 0.0;
+        for (int j0 = 0; j0 < f; j0 += kFbCols) {
+            const int nc = min(kFbCols, f - j0);
+            __syncthreads();
+            for (int e = tid; e < kFbRows * kFbCols; e += kFbRows) {
+                const int r = e / kFbCols, c = e - r * kFbCols;
+                if (r < nr && c < nc) srow[r][c] = src[(int64_t)r * f + j0 + c];
+            }
+            __syncthreads();
+            if (tid < nr)
+                for (int c = 0; c < nc; ++c)
+                    acc = __fma_rn((double)su[j0 + c], (double)srow[tid][c], acc);
+        }
+        if (tid < nr) keys[base + tid] = acc;
+    }
+    __syncthreads();
+}
+
+// Keys of the first a.pre_users fallback users, spread over the device:
+// workgroup (x, y) takes users y, y + gridDim.y, ... and item blocks
+// x, x + gridDim.x, ... of 256 items, one item per thread with its row read
+// directly (a wave's rows are re-read from the cache line by line), the
+// user's row from LDS.  User t's keys go to slot t.
+__global__ void __launch_bounds__(256) fallback_keys_kernel(const FallbackArgs a) {
+    __shared__ float su[256];
+    const unsigned int count = min(a.ctrl->fb_count, (unsigned)a.pre_users);
+    const int64_t nb = (a.n_i + 255) / 256;
+    for (unsigned int t = blockIdx.y; t < count; t += gridDim.y) {
+        const int64_t u = a.flist[t];
+        __syncthreads();
+        for (int j = threadIdx.x; j < a.f; j += 256) su[j] = a.U[u * a.f + j];
+        __syncthreads();
+        for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+            const int64_t i = blk * 256 + threadIdx.x;
+            if (i >= a.n_i) continue;
+            const float* row = a.I + i * a.f;
+            double acc = 0.0;
+            int j = 0;
+            if ((a.f & 1) == 0) {
+                const float2* r2 = (const float2*)row;
+                for (; j + 16 <= a.f; j += 16) {
+                    float2 y[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) y[e] = r2[(j >> 1) + e];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        acc = __fma_rn((double)su[j + 2 * e], (double)y[e].x, acc);
+                        acc = __fma_rn((double)su[j + 2 * e + 1], (double)y[e].y, acc);
+                    }
+                }
+            }
+            for (; j < a.f; ++j) acc = __fma_rn((double)su[j], (double)row[j], acc);
+            a.keys[(int64_t)t * a.n_i + i] = acc;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
     __shared__ unsigned int hist[256];
     __shared__ double skey[kFallbackMaxK];
     __shared__ int sidx[kFallbackMaxK];
+    __shared__ float su[256];
+    __shared__ float srow[kFbRows][kFbCols + 1];
     __shared__ unsigned long long s_prefix;
     __shared__ unsigned int s_need, s_sel, s_wave[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -261,7 +334,11 @@ __global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
     for (unsigned int t = blockIdx.x; t < count; t += gridDim.x) {
         const int64_t u = a.flist[t];
         const float* urow = a.U + u * a.f;
-        for (int64_t i = tid; i < a.n_i; i += 256) keys[i] = dot64(urow, a.I + i * a.f, a.f);
+        __syncthreads();
+        if (t >= (unsigned)a.pre_users) {     // keys not precomputed by fallback_keys_kernel
+            for (int j = tid; j < a.f; j += 256) su[j] = urow[j];
+            fallback_keys(a, su, srow, keys);
+        }
         if (tid == 0) { s_prefix = 0ull; s_need = (unsigned)K; s_sel = 0u; }
         __syncthreads();
         unsigned long long mask = 0ull;
@@ -364,7 +441,16 @@ hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s) {
+hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a_in, hipStream_t s) {
+    // keys of the first fb_grid fallback users across the whole device (each
+    // user's keys land in the slot of the workgroup that selects them), the
+    // rest inside the selection kernel
+    FallbackArgs a = a_in;
+    a.pre_users = p.fb_grid;
+    const unsigned xb = (unsigned)std::min<int64_t>(32, (a.n_i + 255) / 256);
+    fallback_keys_kernel<<<dim3(xb, 16), dim3(256), 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     fallback_kernel<<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }

@@ -70,6 +70,8 @@ struct ScreenArgs {
     const int* pscale;        // FP8: E8M0 scale byte per sorted position
     const float2* blockmax;   // per item tile: (max C, max G)
     const int* perm;          // sorted position -> item index
+    const float* tailmax;     // per tile: max ||i|| over this and all later tiles
+    int prune;                // norm pruning: a user stops once ||u|| tailmax < tau_u
     // Maximus walk
     int walk;
     int warm_rounds;          // warm-up rounds seeding tau (tiles per warm-up set)
@@ -105,6 +107,7 @@ struct FallbackArgs {
     const int* flist;
     Ctrl* ctrl;
     double* keys;             // fb_grid x n_i scratch
+    int pre_users;            // fallback users whose keys a separate kernel computed
     int32_t* out_idx;
     double* out_score;
 };
@@ -134,6 +137,7 @@ constexpr int kFallbackMaxK = 4096;
 // Launchers (each returns hipSuccess or the launch error).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_scan4096(unsigned int* hist, hipStream_t s);
+hipError_t launch_tailmax(const float2* blockmax, int64_t n_blk, float* tailmax, hipStream_t s);
 hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s);
 hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_fp32(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);

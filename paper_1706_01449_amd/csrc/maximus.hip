@@ -22,13 +22,17 @@ namespace mips {
 // ---------------------------------------------------------------------------
 // Small helpers.
 // ---------------------------------------------------------------------------
-__global__ void absmax_kernel(const float* X, int64_t n, unsigned int* out) {
+__global__ void __launch_bounds__(256) absmax_kernel(const float* X, int64_t n, unsigned int* out) {
+    __shared__ float wm[4];
     float m = 0.0f;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         m = fmaxf(m, fabsf(X[i]));
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)   // one atomic per workgroup
+        atomicMax(out, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
 }
 
 // 2^e with n * max|x| * 2^e < 2^61, so fixed-point sums of n values fit in int64.
@@ -171,19 +175,30 @@ __device__ __forceinline__ double stable_angle(const float* a, const double* b, 
 
 // theta_b[c] = max over users of cluster c of the user-centroid angle (zero
 // users left out).  Non-negative doubles order like their bit patterns.
-__global__ void theta_kernel(const float* __restrict__ U, int64_t n_u, int f,
-                             const int* __restrict__ assign, const double* __restrict__ cent,
-                             const double* __restrict__ cnorm, unsigned long long* theta_bits) {
-    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (u >= n_u) return;
-    const float* row = U + u * f;
-    double n2 = 0.0;
-    for (int j = 0; j < f; ++j) n2 += (double)row[j] * (double)row[j];
-    const int c = assign[u];
-    const double nc = cnorm[c];
-    if (!(n2 > 0.0) || !(nc > 0.0)) return;
-    const double th = stable_angle(row, cent + (int64_t)c * f, f, sqrt(n2), nc);
-    atomicMax(&theta_bits[c], (unsigned long long)__double_as_longlong(th));
+// Workgroups stride over many users and keep the per-cluster maxima in LDS,
+// then merge them with one atomic per cluster and workgroup.
+__global__ void __launch_bounds__(256) theta_kernel(const float* __restrict__ U, int64_t n_u, int f,
+                                                    const int* __restrict__ assign,
+                                                    const double* __restrict__ cent,
+                                                    const double* __restrict__ cnorm, int C,
+                                                    unsigned long long* theta_bits) {
+    __shared__ unsigned long long lt[4096];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) lt[c] = 0ull;
+    __syncthreads();
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_u;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const float* row = U + u * f;
+        double n2 = 0.0;
+        for (int j = 0; j < f; ++j) n2 += (double)row[j] * (double)row[j];
+        const int c = assign[u];
+        const double nc = cnorm[c];
+        if (!(n2 > 0.0) || !(nc > 0.0)) continue;
+        const double th = stable_angle(row, cent + (int64_t)c * f, f, sqrt(n2), nc);
+        atomicMax(&lt[c], (unsigned long long)__double_as_longlong(th));
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x)
+        if (lt[c]) atomicMax(&theta_bits[c], lt[c]);
 }
 
 __global__ void cnorm_kernel(const double* cent, int C, int f, double* cnorm) {
@@ -335,14 +350,82 @@ __global__ void cblockmax_kernel(const int* lists, int64_t n_i_pad, int64_t n_bl
     out[t] = make_float2(cm, gm);
 }
 
+// ---------------------------------------------------------------------------
+// Users grouped by cluster, in ascending user order inside each cluster (a
+// stable counting sort on the cluster id, C <= 4096): per-chunk counts,
+// per-cluster running offsets over the chunks, then a scatter that walks each
+// chunk in order, 64 users at a time, ranking equal clusters within the wave.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) group_count_kernel(const int* assign, int64_t n, int64_t chunk,
+                                                          int C, unsigned int* ccounts) {
+    __shared__ unsigned int lc[4096];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) lc[c] = 0u;
+    __syncthreads();
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) atomicAdd(&lc[assign[u]], 1u);
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) ccounts[(int64_t)blockIdx.x * C + c] = lc[c];
+}
+
+// offs[k][c] = sum of ccounts[k'][c] over chunks k' < k; hist[c] = total of c
+__global__ void group_offsets_kernel(unsigned int* ccounts, int nchunks, int C, unsigned int* hist) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    unsigned int run = 0u;
+    for (int k = 0; k < nchunks; ++k) {
+        const unsigned int v = ccounts[(int64_t)k * C + c];
+        ccounts[(int64_t)k * C + c] = run;
+        run += v;
+    }
+    hist[c] = run;
+}
+
+__global__ void __launch_bounds__(64) group_scatter_kernel(const int* assign, int64_t n, int64_t chunk,
+                                                           int C, const unsigned int* offs,
+                                                           const unsigned int* cstart, int* sorted) {
+    __shared__ unsigned int next[4096];
+    const int lane = threadIdx.x;
+    for (int c = lane; c < C; c += 64) next[c] = cstart[c] + offs[(int64_t)blockIdx.x * C + c];
+    __syncthreads();
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = lo; base < hi; base += 64) {
+        const int64_t u = base + lane;
+        const bool on = u < hi;
+        const int key = on ? assign[u] : -1;
+        uint64_t left = ballot(on);
+        while (left) {
+            const int leader = __builtin_ctzll(left);
+            const int k = __builtin_amdgcn_readlane(key, leader);
+            const uint64_t m = ballot(key == k);
+            if (key == k) sorted[next[k] + __builtin_popcountll(m & below)] = (int)u;
+            __syncthreads();
+            if (lane == leader) next[k] += (unsigned int)__builtin_popcountll(m);
+            __syncthreads();
+            left &= ~m;
+        }
+    }
+}
+
 __global__ void iota_kernel(int* v, int64_t n) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t < n) v[t] = (int)t;
 }
 
-__global__ void count_kernel(const int* assign, int64_t n, unsigned int* counts) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < n) atomicAdd(&counts[assign[t]], 1u);
+// Users per cluster.  Each workgroup strides over many users and counts in
+// LDS, then adds its non-zero counts (same-address device atomics are slow,
+// so one per cluster and workgroup instead of one per user).
+__global__ void __launch_bounds__(256) count_kernel(const int* assign, int64_t n, int C,
+                                                    unsigned int* counts) {
+    __shared__ unsigned int lc[4096];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) lc[c] = 0u;
+    __syncthreads();
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&lc[assign[t]], 1u);
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x)
+        if (lc[c]) atomicAdd(&counts[c], lc[c]);
 }
 
 __global__ void set_ctrl_kernel(Ctrl* ctrl, unsigned int c, unsigned int e, unsigned int g) {
@@ -573,7 +656,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         TRY(hipStreamSynchronize(s), "sync");   // `pick` leaves scope
     }
     TRY(launch_zero(absmax, sizeof(unsigned int), s), "zero");
-    absmax_kernel<<<1024, 256, 0, s>>>(ix->U, n_u * f, absmax);
+    absmax_kernel<<<256, 256, 0, s>>>(ix->U, n_u * f, absmax);
     gather_rows_kernel<<<grid_of((int64_t)C * f), 256, 0, s>>>(ix->U, f, init_idx, C, ix->cent);
     const size_t lds_assign = (size_t)64 * f * sizeof(float);
     for (int it = 0; it <= kmeans_iters; ++it) {
@@ -590,8 +673,8 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     // ---- theta_b (Algorithm 1, ConstructIndex) ----------------------------
     cnorm_kernel<<<grid_of(C), 256, 0, s>>>(ix->cent, C, f, cnorm);
     TRY(launch_zero(ix->theta, (size_t)C * sizeof(double), s), "zero");
-    theta_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, ix->cent, cnorm,
-                                              (unsigned long long*)ix->theta);
+    theta_kernel<<<std::min(grid_of(n_u), 1024u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, ix->cent,
+                                                               cnorm, C, (unsigned long long*)ix->theta);
     theta_fix_kernel<<<grid_of(C), 256, 0, s>>>(cnorm, C, ix->theta);
     TRY(hipGetLastError(), "theta_b");
     ix->cent32 = cent32;
@@ -619,17 +702,19 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         lists_kernel<<<grid_of((int64_t)C * ix->n_i_pad), 256, 0, s>>>(k0, v0, n_i, ix->n_i_pad, C,
                                                                        ix->lists, ix->lbound);
         TRY(hipGetLastError(), "lists");
-        // users grouped by cluster: stable sort of (cluster, user) on 16 key bits
-        uint32_t *uk0 = nullptr, *uk1 = nullptr;
-        int *uv1 = nullptr;
-        TRY(dalloc(ix, &uk0, (size_t)n_u), "alloc");
-        TRY(dalloc(ix, &uk1, (size_t)n_u), "alloc");
+        // users grouped by cluster, ascending user order inside each cluster
+        const int64_t chunk = std::max<int64_t>(4096, (n_u + 1023) / 1024);
+        const int nchunks = (int)((n_u + chunk - 1) / chunk);
+        unsigned int *ccounts = nullptr, *ghist = nullptr;
         TRY(dalloc(ix, &ix->sorted_users, (size_t)n_u), "alloc");
-        TRY(dalloc(ix, &uv1, (size_t)n_u), "alloc");
-        TRY(hipMemcpyAsync(uk0, ix->assign, (size_t)n_u * sizeof(int), hipMemcpyDeviceToDevice, s), "copy");
-        iota_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->sorted_users, n_u);
-        radix_pass_kernel<<<1, 1024, 0, s>>>(uk0, ix->sorted_users, uk1, uv1, n_u, 0);
-        radix_pass_kernel<<<1, 1024, 0, s>>>(uk1, uv1, uk0, ix->sorted_users, n_u, 8);
+        TRY(dalloc(ix, &ccounts, (size_t)nchunks * C), "alloc");
+        TRY(dalloc(ix, &ghist, (size_t)2 * kBuckets), "alloc");
+        TRY(launch_zero(ghist, (size_t)2 * kBuckets * sizeof(unsigned int), s), "zero");
+        group_count_kernel<<<nchunks, 256, 0, s>>>(ix->assign, n_u, chunk, C, ccounts);
+        group_offsets_kernel<<<grid_of(C), 256, 0, s>>>(ccounts, nchunks, C, ghist);
+        TRY(launch_scan4096(ghist, s), "scan");
+        group_scatter_kernel<<<nchunks, 64, 0, s>>>(ix->assign, n_u, chunk, C, ccounts,
+                                                    ghist + kBuckets, ix->sorted_users);
         TRY(hipGetLastError(), "user grouping");
     }
 
@@ -694,7 +779,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     // ---- walk tiles: runs of up to 32*UB users of one cluster --------------
     {
         TRY(launch_zero(counts, (size_t)C * sizeof(unsigned int), s), "zero");
-        count_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->assign, n_u, counts);
+        count_kernel<<<std::min(grid_of(n_u), 256u), 256, 0, s>>>(ix->assign, n_u, C, counts);
         std::vector<unsigned int> hc(C);
         TRY(hipMemcpyAsync(hc.data(), counts, C * sizeof(unsigned int), hipMemcpyDeviceToHost, s), "read counts");
         TRY(hipStreamSynchronize(s), "sync");

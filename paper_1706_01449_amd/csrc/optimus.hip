@@ -49,16 +49,19 @@ uint64_t splitmix(uint64_t& x) {
     return z ^ (z >> 31);
 }
 
-// Device buffers released when the scope ends.
+// Stream-ordered device buffers (the runtime's pool makes repeated calls
+// cheap), released on the stream when the scope ends.
 struct Scratch {
+    hipStream_t s;
     std::vector<void*> p;
+    explicit Scratch(hipStream_t st) : s(st) {}
     ~Scratch() {
-        for (void* q : p) (void)hipFree(q);
+        for (void* q : p) (void)hipFreeAsync(q, s);
     }
     template <typename T>
     hipError_t alloc(T** out, size_t count) {
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 256));
+        hipError_t e = hipMallocAsync(&q, std::max<size_t>(count * sizeof(T), 256), s);
         if (e == hipSuccess) {
             p.push_back(q);
             *out = (T*)q;
@@ -113,19 +116,26 @@ extern "C" int mips_optimus_topk(const float* U, int64_t n_u, const float* I, in
     const int64_t kDefaultSample = 131072;
     int64_t ns = sample_users > 0 ? sample_users : std::max<int64_t>(kDefaultSample, n_u / 100);
     ns = std::min(ns, n_u);
+    // systematic sample with a seeded phase: users floor((k + phase) n_u / ns),
+    // k = 0 .. ns-1 (sorted, evenly spread), then the other users in order
     std::vector<int> perm(n_u);
-    for (int64_t i = 0; i < n_u; ++i) perm[i] = (int)i;
-    uint64_t st = seed ^ 0x6f7074696d7573ull;
-    for (int64_t i = 0; i < ns; ++i) {   // partial Fisher-Yates
-        const int64_t j = i + (int64_t)(splitmix(st) % (uint64_t)(n_u - i));
-        std::swap(perm[i], perm[j]);
+    {
+        uint64_t st = seed ^ 0x6f7074696d7573ull;
+        const double phase = (double)(splitmix(st) >> 11) * 0x1p-53;
+        std::vector<unsigned char> in(n_u, 0);
+        for (int64_t k = 0; k < ns; ++k) {
+            const int64_t u = std::min<int64_t>(n_u - 1, (int64_t)(((double)k + phase) * (double)n_u / (double)ns));
+            perm[k] = (int)u;
+            in[u] = 1;
+        }
+        int64_t r = ns;
+        for (int64_t u = 0; u < n_u; ++u)
+            if (!in[u]) perm[r++] = (int)u;
     }
-    std::sort(perm.begin(), perm.begin() + ns);
-    std::sort(perm.begin() + ns, perm.end());
     const int64_t nr = n_u - ns;
     rep.sample_users = ns;
 
-    Scratch sc;
+    Scratch sc(s);
     hipError_t e;
     int* ids = nullptr;
     float *Us = nullptr, *Ur = nullptr;

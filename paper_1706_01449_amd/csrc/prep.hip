@@ -3,7 +3,7 @@
 // operand order with per-tile bound maxima.
 //
 // Why a norm order: the paper's brute force scores items in storage order
-// (Section II-B).  Here the items are streamed in roughly descending ||i||
+// (Section II-C).  Here the items are streamed in roughly descending ||i||
 // so that each user's K-th best score is found early; after that almost no
 // score of a 32 x 32 tile can reach it and the fused top-K stays on its fast
 // path.  The order changes speed only: the final order is decided by the
@@ -264,6 +264,38 @@ __global__ void nonfinite_scan_kernel(const float* U, int64_t nu, const float* I
     for (int64_t j = i; j < nu; j += stride) bad = bad || !__builtin_isfinite(U[j]);
     for (int64_t j = i; j < ni; j += stride) bad = bad || !__builtin_isfinite(I[j]);
     if (bad) atomicOr(&ctrl->nonfinite, 1u);
+}
+
+// Suffix maxima of the per-tile norm maxima (one 1024-thread workgroup:
+// each thread owns a contiguous run of tiles).
+__global__ void __launch_bounds__(1024) tailmax_kernel(const float2* blockmax, int64_t n_blk,
+                                                       float* tailmax) {
+    __shared__ float part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n_blk + 1023) / 1024;
+    const int64_t lo = t * per, hi = lo + per < n_blk ? lo + per : n_blk;
+    float m = 0.0f;
+    for (int64_t b = lo; b < hi; ++b) m = fmaxf(m, blockmax[b].x);
+    part[t] = m;
+    __syncthreads();
+    // inclusive suffix max over the threads' runs (Hillis-Steele), then
+    // exclusive by reading the next thread's entry
+    for (int off = 1; off < 1024; off <<= 1) {
+        const float o = (t + off < 1024) ? part[t + off] : 0.0f;
+        __syncthreads();
+        part[t] = fmaxf(part[t], o);
+        __syncthreads();
+    }
+    float after = (t + 1 < 1024) ? part[t + 1] : 0.0f;
+    for (int64_t b = hi - 1; b >= lo; --b) {
+        after = fmaxf(after, blockmax[b].x);
+        tailmax[b] = after;
+    }
+}
+
+hipError_t launch_tailmax(const float2* blockmax, int64_t n_blk, float* tailmax, hipStream_t s) {
+    tailmax_kernel<<<1, 1024, 0, s>>>(blockmax, n_blk, tailmax);
+    return hipGetLastError();
 }
 
 // Exclusive scan of 4096 counts at hist[0..4096) into hist[4096..8192).

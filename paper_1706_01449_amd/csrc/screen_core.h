@@ -1,5 +1,5 @@
 // Score tiles on the matrix cores fused with a per-user streaming top-K
-// (the brute force of paper Section II-B and the blocked walk of Maximus,
+// (the brute force of paper Section II-C and the blocked walk of Maximus,
 // Section III-C/III-D), then certification with a float64 rescore, and the
 // exact float64 fallback.
 //
@@ -118,6 +118,13 @@ __device__ __forceinline__ int64_t user_of(const ScreenArgs& a, int UB, int64_t 
     return *valid ? u : 0;
 }
 
+// Maximum / minimum that propagate NaN (IEEE 754-2019 maximum): they map to
+// the three-input v_maximum3 / v_minimum3 without the operand quieting that
+// fmaxf needs.  Scores are finite or -inf here (a NaN only arises from
+// non-finite input, whose users are sent to the exact path).
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+
 // Entry `idx` (wave-uniform, known only at run time) of a register list
 // sorted in descending order: the max over the entries from idx on.  Written
 // as a masked reduction so that the list stays in registers (a select chain
@@ -126,7 +133,7 @@ template <int KM>
 __device__ __forceinline__ float pick_sorted(const float (&l)[KM], int idx) {
     float v = -__builtin_inff();
 #pragma unroll
-    for (int q = 0; q < KM; ++q) v = fmaxf(v, (q >= idx) ? l[q] : -__builtin_inff());
+    for (int q = 0; q < KM; ++q) v = vmax(v, (q >= idx) ? l[q] : -__builtin_inff());
     return v;
 }
 
@@ -137,7 +144,7 @@ template <int KM>
 __device__ __forceinline__ void list_insert(float (&l)[KM], float x) {
 #pragma unroll
     for (int q = KM - 1; q >= 1; --q) l[q] = __builtin_amdgcn_fmed3f(l[q - 1], l[q], x);
-    l[0] = fmaxf(l[0], x);
+    l[0] = vmax(l[0], x);
 }
 
 template <int KM>
@@ -154,7 +161,7 @@ __device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
     const float t = l[KM - 1];
     const float th = pick_sorted(l, hidx);
     const float tp = xor32_f(t), thp = xor32_f(th);
-    return fmaxf(fmaxf(t, tp), fminf(th, thp));
+    return vmax(vmax(t, tp), vmin(th, thp));
 }
 
 // Warm-up sets of per-slot maxima (16 slots per set) used to seed tau.
@@ -186,7 +193,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     Op bu[UB][NCH];
     float Au[UB], Bu[UB], slk[UB], tau[UB], tauf[UB], Nup[UB];
-    int64_t ustop[UB];            // walk: tiles visited before the user stopped
+    int ustop[UB];                // walk: tiles visited before the user stopped
     float lst[UB][KM];
     int cnt[UB], uscale[UB];
     bool act[UB];
@@ -294,16 +301,16 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
     const int hidx = KM - (a.K / 2) - 1;
-    const int64_t n_blk = a.n_blk;
+    const int n_blk = (int)a.n_blk;   // < 2^26 (n_i < 2^31): 32-bit scalar tile arithmetic
     const int* clist = WALK ? a.lists + (int64_t)cluster * a.n_i_pad : nullptr;
     // per-tile bound maxima (prefetched with the tile operands)
     const float2* bmax = WALK ? a.cblockmax + (int64_t)cluster * n_blk : a.blockmax;
 
     // This lane's A-operand chunks of tile b (row n), the row's item index
     // (-1 past the end) and, for E4M3, the row's E8M0 scale byte.
-    auto load_tile = [&](int64_t b, Op (&ai)[NCH], int& item, int& iscale, float2& bm)
+    auto load_tile = [&](int b, Op (&ai)[NCH], int& item, int& iscale, float2& bm)
         __attribute__((always_inline)) {
-        const int64_t p = b * kTile + n;
+        const int64_t p = (int64_t)b * kTile + n;
         bm = bmax[b];
         if constexpr (!WALK) {
 #pragma unroll
@@ -325,7 +332,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // Score tile: acc[ub] = items (rows) x users (columns); rows past the
     // last item are set to -inf.
-    auto score_tile = [&](int64_t b, const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB])
+    auto score_tile = [&](int b, const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB])
         __attribute__((always_inline)) {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
@@ -335,12 +342,12 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             for (int c = 0; c < NCH; ++c)
                 acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
         }
-        if ((b + 1) * kTile > a.n_i) {
+        if ((int64_t)(b + 1) * kTile > a.n_i) {
 #pragma unroll
             for (int ub = 0; ub < UB; ++ub)
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if (b * kTile + 8 * (r >> 2) + 4 * h + (r & 3) >= a.n_i) acc[ub][r] = ninf;
+                    if ((int64_t)b * kTile + 8 * (r >> 2) + 4 * h + (r & 3) >= a.n_i) acc[ub][r] = ninf;
         }
     };
 
@@ -359,7 +366,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         for (int rd = 0; rd < a.warm_rounds; ++rd) {
 #pragma unroll
             for (int sidx = 0; sidx < S; ++sidx) {
-                const int64_t b = (int64_t)rd * S + sidx;
+                const int b = rd * S + sidx;
                 if (b < n_blk) {
                     Op ai[NCH];
                     int it = -1, sc = 127;
@@ -371,7 +378,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     for (int ub = 0; ub < UB; ++ub)
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
-                            gm[ub][sidx * 16 + r] = fmaxf(gm[ub][sidx * 16 + r], acc[ub][r]);
+                            gm[ub][sidx * 16 + r] = vmax(gm[ub][sidx * 16 + r], acc[ub][r]);
                 }
             }
         }
@@ -389,7 +396,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // Streaming top-K over tile b; returns false once every user of a walk
     // wave has stopped.
-    auto epi_tile = [&](int64_t b, floatx16_t (&acc)[UB], int item, float2 bm)
+    auto epi_tile = [&](int b, floatx16_t (&acc)[UB], int item, float2 bm)
         __attribute__((always_inline)) -> bool {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
@@ -399,9 +406,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             float gm4[4];
 #pragma unroll
             for (int g = 0; g < 4; ++g)
-                gm4[g] = fmaxf(fmaxf(acc[ub][4 * g], acc[ub][4 * g + 1]),
-                               fmaxf(acc[ub][4 * g + 2], acc[ub][4 * g + 3]));
-            const float m = fmaxf(fmaxf(gm4[0], gm4[1]), fmaxf(gm4[2], gm4[3]));
+                gm4[g] = vmax(vmax(acc[ub][4 * g], acc[ub][4 * g + 1]),
+                              vmax(acc[ub][4 * g + 2], acc[ub][4 * g + 3]));
+            const float m = vmax(vmax(gm4[0], gm4[1]), vmax(gm4[2], gm4[3]));
             if (ballot(m >= thr)) {
                 // a group is walked only when some lane's group maximum passes
 #pragma unroll
@@ -425,19 +432,26 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         }
                     }
                 }
-                tau[ub] = fmaxf(tau[ub], list_tau(lst[ub], hidx));
+                tau[ub] = vmax(tau[ub], list_tau(lst[ub], hidx));
                 tauf[ub] = act[ub] ? tau[ub] : pinf;
             }
         }
-        if constexpr (!WALK) return true;
+        if constexpr (!WALK) {
+            if (!a.prune) return true;
+        }
         // Stop test after this tile (Section III-C): every unvisited item i has
         // key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is sorted,
-        // so the next entry's bound covers all of them.
-        const int64_t pnext = (b + 1) * kTile;
+        // so the next entry's bound covers all of them.  The norm-pruned brute
+        // force is the same test with theta_b = pi (bound = ||i||), over the
+        // suffix maxima of its norm-ordered tiles.
+        const int64_t pnext = (int64_t)(b + 1) * kTile;
         bool any = false;
-        if (b + 1 >= a.shared_blocks) {
-            const float bnext =
-                (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
+        if (b + 1 >= (WALK ? a.shared_blocks : 1)) {
+            float bnext;
+            if constexpr (WALK)
+                bnext = (pnext < a.n_i) ? a.lbound[(int64_t)cluster * a.n_i_pad + pnext] : ninf;
+            else
+                bnext = (b + 1 < n_blk) ? a.tailmax[b + 1] : ninf;
 #pragma unroll
             for (int ub = 0; ub < UB; ++ub) {
                 if (act[ub] && fmaf(Nup[ub], bnext, slk[ub]) < tau[ub]) {
@@ -458,16 +472,16 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // Operands are loaded two tiles ahead into alternating register sets; the
     // loads are unconditional (tile index clamped to the last tile) so the
     // loop body is straight-line code with exact wait counts.
-    int64_t b_done = n_blk;       // tiles visited (the walk may stop early)
+    int b_done = n_blk;           // tiles visited (the walk may stop early)
     if (n_blk > 0) {
-        const int64_t last = n_blk - 1;
+        const int last = n_blk - 1;
         Op oA[NCH], oB[NCH];
         int itA = -1, itB = -1, scA = 127, scB = 127;
         float2 bmA, bmB;
         floatx16_t acc[UB];
         load_tile(0, oA, itA, scA, bmA);
         load_tile(n_blk > 1 ? 1 : 0, oB, itB, scB, bmB);
-        for (int64_t b = 0; b < n_blk; b += 2) {
+        for (int b = 0; b < n_blk; b += 2) {
             score_tile(b, oA, scA, acc);
             const int eA = itA;
             const float2 mA = bmA;

@@ -90,6 +90,8 @@ def lib():
     L.mips_bmm_topk.restype = ctypes.c_int
     L.mips_bmm_topk.argtypes = [vp, c_i64, vp, c_i64, c_i32, c_i32, c_i32, vp, vp, vp, c_sz, vp,
                                 ctypes.POINTER(Stats)]
+    L.mips_norm_pruned_topk.restype = ctypes.c_int
+    L.mips_norm_pruned_topk.argtypes = L.mips_bmm_topk.argtypes
     L.mips_maximus_build.restype = ctypes.c_int
     L.mips_maximus_build.argtypes = [vp, c_i64, vp, c_i64, c_i32, c_i32, c_i32, c_u64, c_i32, vp,
                                      ctypes.POINTER(vp)]
@@ -160,6 +162,17 @@ def bmm_topk(U: torch.Tensor, I: torch.Tensor, K: int, precision="bf16", stats: 
     """Exact top-K items of every user by brute force (blocked matrix multiply
     fused with a streaming top-K).  Returns (idx int32 [n_u, K], score float64
     [n_u, K]) and, with ``stats=True``, a dict of counters (synchronises)."""
+    return _bmm_call("mips_bmm_topk", U, I, K, precision, stats, workspace)
+
+
+def norm_pruned_topk(U: torch.Tensor, I: torch.Tensor, K: int, precision="bf16",
+                     stats: bool = False, workspace: torch.Tensor | None = None):
+    """Brute force with per-user early termination on the item norms (the
+    Maximus stop test with theta_b = pi).  Same result as bmm_topk."""
+    return _bmm_call("mips_norm_pruned_topk", U, I, K, precision, stats, workspace)
+
+
+def _bmm_call(fn: str, U, I, K, precision, stats, workspace):
     U = _mat(U, "U")
     I = _mat(I, "I")
     if U.shape[1] != I.shape[1]:
@@ -180,9 +193,9 @@ def bmm_topk(U: torch.Tensor, I: torch.Tensor, K: int, precision="bf16", stats: 
     idx = torch.empty((n_u, K), dtype=torch.int32, device=U.device)
     score = torch.empty((n_u, K), dtype=torch.float64, device=U.device)
     st = Stats() if stats else None
-    rc = L.mips_bmm_topk(U.data_ptr(), n_u, I.data_ptr(), n_i, f, int(K), p, idx.data_ptr(),
-                         score.data_ptr(), workspace.data_ptr(), workspace.numel(),
-                         _stream(U.device), ctypes.byref(st) if st is not None else None)
+    rc = getattr(L, fn)(U.data_ptr(), n_u, I.data_ptr(), n_i, f, int(K), p, idx.data_ptr(),
+                        score.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                        _stream(U.device), ctypes.byref(st) if st is not None else None)
     _check(rc)
     if stats:
         return idx, score, st.as_dict()

@@ -187,3 +187,43 @@ def test_forced_candidate_overflow_stays_exact(prec, monkeypatch):
     monkeypatch.delenv("MIPS_DEBUG_CAND_CAP")
     assert st["overflow_users"] > 600
     assert_parity(idx, score, U, I, 10)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(300, 1000, 16, 10), (257, 3001, 50, 1), (129, 2000, 100, 50)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_norm_pruned_small(prec, shape):
+    """Norm-pruned brute force (stop test with theta_b = pi) returns the
+    oracle's answer; ragged shapes, ties from duplicate rows, a zero row."""
+    import paper_1706_01449_amd as mips
+    import torch
+    from gpu_util import to_dev
+    n_u, n_i, f, K = shape
+    U, I = mipsgen.generate("mf", 12, n_users=n_u, n_items=n_i, f=f)
+    I[7] = I[3]
+    U[2] = 0.0
+    Ut, It = to_dev(U, I)
+    idx, sc, st = mips.norm_pruned_topk(Ut, It, K, prec, stats=True)
+    torch.cuda.synchronize()
+    assert_parity(idx.cpu().numpy(), sc.cpu().numpy(), U, I, K)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_norm_pruned_mf_full_size(prec):
+    """480,000 x 17,770, f = 50, K = 10: equal to the brute force on every
+    user, oracle parity on sampled users, fewer items scored."""
+    import paper_1706_01449_amd as mips
+    import torch
+    from gpu_util import to_dev
+    U, I = _mf_full()
+    Ut, It = to_dev(U, I)
+    a = mips.bmm_topk(Ut, It, 10, prec)
+    idx, sc, st = mips.norm_pruned_topk(Ut, It, 10, prec, stats=True)
+    torch.cuda.synchronize()
+    log(f"  stats {st}")
+    idx, sc = idx.cpu().numpy(), sc.cpu().numpy()
+    np.testing.assert_array_equal(idx, a[0].cpu().numpy())
+    np.testing.assert_array_equal(sc, a[1].cpu().numpy())
+    users = mipsgen.sample_users(U.shape[0], 500, seed=31)
+    assert_parity(idx, sc, U, I, 10, users=users)
+    assert st["mean_items_visited"] < I.shape[0]

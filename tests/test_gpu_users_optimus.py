@@ -45,7 +45,9 @@ def test_query_users_new_users(prec, K):
     log(f"query_users new users prec={prec} K={K}")
     U, I = mipsgen.generate("clustered", 5, n_users=6000, n_items=3000, f=24)
     ix = _build(U, I, 32)
-    fresh, _ = mipsgen.generate("clustered", 6, n_users=700, n_items=1, f=24)
+    # same seed, more users: the same mixture components, fresh draws
+    more, _ = mipsgen.generate("clustered", 5, n_users=6700, n_items=3000, f=24)
+    fresh = more[6000:]
     far, _ = mipsgen.generate("tiny", 7, n_users=300, n_items=1, f=24)
     Uq = np.concatenate([fresh, far * 5.0, np.zeros((1, 24), np.float32), fresh[:50] * 1e3,
                          U[::37]]).astype(np.float32)
@@ -55,6 +57,9 @@ def test_query_users_new_users(prec, K):
     idx, sc = idx.cpu().numpy(), sc.cpu().numpy()
     assert_parity(idx, sc, Uq, I, K)
     log(f"  stats {st}")
+    # the zero row takes the exact path, as do far rows outside every
+    # cluster's cone; most fresh draws of the same mixture are covered
+    assert 1 <= st["overflow_users"] <= Uq.shape[0] - 500
 
 
 def test_query_users_zero_and_single_row():

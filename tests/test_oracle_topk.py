@@ -1,6 +1,6 @@
 """Pins for the top-K oracle (CPU only).
 
-The oracle's result definition is the brute force of Section II-B evaluated
+The oracle's result definition is the brute force of Section II-C evaluated
 in float64 with a fixed left-to-right sum and ties to the lower item index.
 It is pinned here by things other than itself: exact rational arithmetic on
 tiny inputs, an independent numpy evaluation, and closed forms.
