@@ -349,7 +349,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
     a.gamma = p.gamma;
     a.ctrl = ctrl;
     a.want_stats = stats != nullptr;
-    a.warm_rounds = 8;
+    a.warm_rounds = 6;
     a.uflag = (int*)(ws + L.uflag);
     a.flist = (int*)(ws + L.flist);
     a.uscal = (float4*)(ws + L.uscal);

@@ -106,21 +106,19 @@ __device__ __forceinline__ uint64_t ballot(bool p) {
     return __builtin_amdgcn_ballot_w64(p);
 }
 
-__device__ __forceinline__ float xor32_f(float v) {
-    // value held by lane (lane ^ 32)
-    int lane = __lane_id();
-    return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(v)));
+// Value held by lane (lane ^ 32), by the VALU lane-swap of the two wave
+// halves (v_permlane32_swap: with both operands equal, the first result holds
+// the lower half's values in both halves and the second the upper half's).
+__device__ __forceinline__ uint32_t xor32_u(uint32_t v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (__lane_id() < 32) ? r[1] : r[0];
 }
-__device__ __forceinline__ int xor32_i(int v) {
-    int lane = __lane_id();
-    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
-}
+__device__ __forceinline__ float xor32_f(float v) { return __uint_as_float(xor32_u(__float_as_uint(v))); }
+__device__ __forceinline__ int xor32_i(int v) { return (int)xor32_u((uint32_t)v); }
 __device__ __forceinline__ double xor32_d(double v) {
-    int lane = __lane_id();
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-    int lo = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(uint32_t)b);
-    int hi = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(uint32_t)(b >> 32));
-    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = xor32_u((uint32_t)b), hi = xor32_u((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Order-preserving maps for atomic max on non-negative floating point.

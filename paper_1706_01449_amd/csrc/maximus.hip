@@ -407,6 +407,45 @@ __global__ void __launch_bounds__(64) group_scatter_kernel(const int* assign, in
     }
 }
 
+// Fixed-point per-cluster sums over users already grouped by cluster:
+// workgroup w takes sorted positions [w * 2048, (w + 1) * 2048), thread t
+// factor t % f of rows t / f, t / f + 256 / f, ...; a thread adds its partial
+// sum to the cluster's global sum only when the cluster changes along its
+// rows, so a workgroup issues about f atomics per cluster it touches.
+constexpr int kSortedSumRows = 2048;
+
+__global__ void __launch_bounds__(256) kmeans_sum_sorted_kernel(const float* __restrict__ U,
+                                                                int64_t n_u, int f,
+                                                                const int* __restrict__ sorted,
+                                                                const int* __restrict__ assign,
+                                                                const unsigned int* absmax_bits,
+                                                                unsigned long long* sums) {
+    const int per = 256 / f;                 // rows per pass (f <= 256)
+    const int r0 = threadIdx.x / f, j = threadIdx.x - r0 * f;
+    if (r0 >= per) return;
+    const double scale = fixed_scale(n_u, *absmax_bits);
+    const int64_t lo = (int64_t)blockIdx.x * kSortedSumRows;
+    const int64_t hi = lo + kSortedSumRows < n_u ? lo + kSortedSumRows : n_u;
+    long long acc = 0;
+    int cur = -1;
+    for (int64_t p = lo + r0; p < hi; p += per) {
+        const int u = sorted[p];
+        const int c = assign[u];
+        if (c != cur) {
+            if (cur >= 0 && acc) atomicAdd(&sums[(int64_t)cur * f + j], (unsigned long long)acc);
+            acc = 0;
+            cur = c;
+        }
+        acc += llrint((double)U[(int64_t)u * f + j] * scale);
+    }
+    if (cur >= 0 && acc) atomicAdd(&sums[(int64_t)cur * f + j], (unsigned long long)acc);
+}
+
+__global__ void copy_counts_kernel(const unsigned int* hist, int C, unsigned int* counts) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) counts[c] = hist[c];
+}
+
 __global__ void iota_kernel(int* v, int64_t n) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t < n) v[t] = (int)t;
@@ -437,6 +476,25 @@ __global__ void set_ctrl_kernel(Ctrl* ctrl, unsigned int c, unsigned int e, unsi
 }
 
 static unsigned int grid_of(int64_t n, int b = 256) { return (unsigned int)((n + b - 1) / b); }
+
+// Users grouped by cluster (ascending user order inside each cluster) into
+// `sorted`; ghist[0..C) receives the cluster sizes and ghist[4096 + c] the
+// first position of cluster c.  ccounts holds group_chunks(n_u) * C entries.
+static int64_t group_chunk(int64_t n_u) { return std::max<int64_t>(4096, (n_u + 1023) / 1024); }
+static int group_chunks(int64_t n_u) { return (int)((n_u + group_chunk(n_u) - 1) / group_chunk(n_u)); }
+
+static hipError_t group_users(const int* assign, int64_t n_u, int C, unsigned int* ccounts,
+                              unsigned int* ghist, int* sorted, hipStream_t s) {
+    const int64_t chunk = group_chunk(n_u);
+    const int nchunks = group_chunks(n_u);
+    hipError_t e = launch_zero(ghist, (size_t)2 * kBuckets * sizeof(unsigned int), s);
+    if (e != hipSuccess) return e;
+    group_count_kernel<<<nchunks, 256, 0, s>>>(assign, n_u, chunk, C, ccounts);
+    group_offsets_kernel<<<grid_of(C), 256, 0, s>>>(ccounts, nchunks, C, ghist);
+    if ((e = launch_scan4096(ghist, s)) != hipSuccess) return e;
+    group_scatter_kernel<<<nchunks, 64, 0, s>>>(assign, n_u, chunk, C, ccounts, ghist + kBuckets, sorted);
+    return hipGetLastError();
+}
 
 }  // namespace mips
 
@@ -646,6 +704,12 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     TRY(dalloc(ix, &absmax, 1), "alloc");
     TRY(dalloc(ix, &sums, (size_t)C * f), "alloc");
     TRY(dalloc(ix, &counts, (size_t)C), "alloc");
+    unsigned int *ccounts = nullptr, *ghist = nullptr;
+    TRY(dalloc(ix, &ix->sorted_users, (size_t)n_u), "alloc");
+    TRY(dalloc(ix, &ccounts, (size_t)group_chunks(n_u) * C), "alloc");
+    TRY(dalloc(ix, &ghist, (size_t)2 * kBuckets), "alloc");
+    // sums in LDS per workgroup when C x f fits, else over users grouped by cluster
+    const bool lds_sums = (int64_t)C * f <= 4096;
     TRY(dalloc(ix, &cent32, (size_t)C * f), "alloc");
     TRY(dalloc(ix, &cnorm2, (size_t)C), "alloc");
     TRY(dalloc(ix, &cnorm, (size_t)C), "alloc");
@@ -665,7 +729,14 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         if (it == kmeans_iters) break;   // final assignment after the last update
         TRY(launch_zero(sums, (size_t)C * f * sizeof(unsigned long long), s), "zero");
         TRY(launch_zero(counts, (size_t)C * sizeof(unsigned int), s), "zero");
-        kmeans_sum_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, absmax, sums, counts, C);
+        if (lds_sums) {
+            kmeans_sum_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, absmax, sums, counts, C);
+        } else {
+            TRY(group_users(ix->assign, n_u, C, ccounts, ghist, ix->sorted_users, s), "grouping");
+            kmeans_sum_sorted_kernel<<<grid_of(n_u, kSortedSumRows), 256, 0, s>>>(
+                ix->U, n_u, f, ix->sorted_users, ix->assign, absmax, sums);
+            copy_counts_kernel<<<grid_of(C), 256, 0, s>>>(ghist, C, counts);
+        }
         kmeans_update_kernel<<<grid_of((int64_t)C * f), 256, 0, s>>>(ix->cent, C, f, sums, counts, absmax, n_u);
     }
     TRY(hipGetLastError(), "k-means");
@@ -702,20 +773,8 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         lists_kernel<<<grid_of((int64_t)C * ix->n_i_pad), 256, 0, s>>>(k0, v0, n_i, ix->n_i_pad, C,
                                                                        ix->lists, ix->lbound);
         TRY(hipGetLastError(), "lists");
-        // users grouped by cluster, ascending user order inside each cluster
-        const int64_t chunk = std::max<int64_t>(4096, (n_u + 1023) / 1024);
-        const int nchunks = (int)((n_u + chunk - 1) / chunk);
-        unsigned int *ccounts = nullptr, *ghist = nullptr;
-        TRY(dalloc(ix, &ix->sorted_users, (size_t)n_u), "alloc");
-        TRY(dalloc(ix, &ccounts, (size_t)nchunks * C), "alloc");
-        TRY(dalloc(ix, &ghist, (size_t)2 * kBuckets), "alloc");
-        TRY(launch_zero(ghist, (size_t)2 * kBuckets * sizeof(unsigned int), s), "zero");
-        group_count_kernel<<<nchunks, 256, 0, s>>>(ix->assign, n_u, chunk, C, ccounts);
-        group_offsets_kernel<<<grid_of(C), 256, 0, s>>>(ccounts, nchunks, C, ghist);
-        TRY(launch_scan4096(ghist, s), "scan");
-        group_scatter_kernel<<<nchunks, 64, 0, s>>>(ix->assign, n_u, chunk, C, ccounts,
-                                                    ghist + kBuckets, ix->sorted_users);
-        TRY(hipGetLastError(), "user grouping");
+        // users grouped by the final assignment
+        TRY(group_users(ix->assign, n_u, C, ccounts, ghist, ix->sorted_users, s), "user grouping");
     }
 
     // ---- screen copies of the items for every precision --------------------

@@ -166,7 +166,7 @@ __device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
 
 // Warm-up sets of per-slot maxima (16 slots per set) used to seed tau.
 __host__ __device__ constexpr int warm_sets(int km) {
-    return km <= 10 ? 1 : (km <= 16 ? 2 : (km <= 32 ? 3 : 4));
+    return km <= 16 ? 2 : (km <= 32 ? 3 : 4);
 }
 
 // ---------------------------------------------------------------------------
