@@ -11,78 +11,6 @@ namespace mips {
 // rescore them in float64 (left to right), and emit the first K by
 // (key desc, item index asc).  Same wave/user mapping as the screen.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
-    return ka > kb || (ka == kb && ia < ib);
-}
-
-// float64 key of (u, i) summed left to right; the row loads are issued in
-// batches of 16 factors so that one memory latency covers 16 FMAs.
-__device__ __forceinline__ double key64(const float* __restrict__ u, const float* __restrict__ v,
-                                        int f) {
-    double acc = 0.0;
-    int j = 0;
-    if ((f & 1) == 0) {
-        const float2* u2 = (const float2*)u;
-        const float2* v2 = (const float2*)v;
-        for (; j + 16 <= f; j += 16) {
-            float2 x[8], y[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) { x[q] = u2[(j >> 1) + q]; y[q] = v2[(j >> 1) + q]; }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                acc = __fma_rn((double)x[q].x, (double)y[q].x, acc);
-                acc = __fma_rn((double)x[q].y, (double)y[q].y, acc);
-            }
-        }
-    }
-    for (; j < f; ++j) acc = __fma_rn((double)u[j], (double)v[j], acc);
-    return acc;
-}
-
-// float64 keys of u against up to four item rows (it[q] < 0: skipped), each
-// summed left to right; the loads of all rows of an 8-factor batch are
-// issued together, so one memory latency covers up to 32 FMAs.
-__device__ __forceinline__ void keys4(const float* __restrict__ u, const float* __restrict__ I,
-                                      int f, const int (&it)[4], double (&acc)[4]) {
-    const float* v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v[q] = I + (int64_t)(it[q] >= 0 ? it[q] : 0) * f;
-        acc[q] = 0.0;
-    }
-    int j = 0;
-    if ((f & 1) == 0) {
-        const float2* u2 = (const float2*)u;
-        for (; j + 8 <= f; j += 8) {
-            float2 x[4], y[4][4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[e] = u2[(j >> 1) + e];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (it[q] < 0) continue;
-                const float2* v2 = (const float2*)v[q];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) y[q][e] = v2[(j >> 1) + e];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (it[q] < 0) continue;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    acc[q] = __fma_rn((double)x[e].x, (double)y[q][e].x, acc[q]);
-                    acc[q] = __fma_rn((double)x[e].y, (double)y[q][e].y, acc[q]);
-                }
-            }
-        }
-    }
-    for (; j < f; ++j) {
-        const double x = (double)u[j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (it[q] >= 0) acc[q] = __fma_rn(x, (double)v[q][j], acc[q]);
-    }
-}
-
 // G lanes per user (a group, contiguous in the wave), EM kept pairs per lane.
 // The screen left each user two candidate lists (its two lanes' halves);
 // lane g of the group takes entries g, g+G, ... of their concatenation,
@@ -420,6 +348,7 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 
 // Per-user bin of kept candidates in certification (LDS).
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
+    if (fused_certify(p.prec, p.KM, p.UB)) return hipSuccess;   // done by the screen kernel
     // lanes per user G and LDS slots per lane EM (pairs whose key reaches
     // tau_u): 64 per user for the float32/bfloat16 screens at K <= 16, 256
     // for larger K or E4M3 at K <= 16, 1024 for E4M3 at larger K

@@ -97,6 +97,80 @@ __device__ __forceinline__ double dot64(const float* __restrict__ u, const float
     return acc;
 }
 
+// Order of the result: a before b iff a has the larger key, or equal keys
+// and the lower item index.
+__device__ __forceinline__ bool before(double ka, int ia, double kb, int ib) {
+    return ka > kb || (ka == kb && ia < ib);
+}
+
+// float64 key of (u, i) summed left to right; the row loads are issued in
+// batches of 16 factors so that one memory latency covers 16 FMAs.
+__device__ __forceinline__ double key64(const float* __restrict__ u, const float* __restrict__ v,
+                                        int f) {
+    double acc = 0.0;
+    int j = 0;
+    if ((f & 1) == 0) {
+        const float2* u2 = (const float2*)u;
+        const float2* v2 = (const float2*)v;
+        for (; j + 16 <= f; j += 16) {
+            float2 x[8], y[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) { x[q] = u2[(j >> 1) + q]; y[q] = v2[(j >> 1) + q]; }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc = __fma_rn((double)x[q].x, (double)y[q].x, acc);
+                acc = __fma_rn((double)x[q].y, (double)y[q].y, acc);
+            }
+        }
+    }
+    for (; j < f; ++j) acc = __fma_rn((double)u[j], (double)v[j], acc);
+    return acc;
+}
+
+// float64 keys of u against up to four item rows (it[q] < 0: skipped), each
+// summed left to right; the loads of all rows of an 8-factor batch are
+// issued together, so one memory latency covers up to 32 FMAs.
+__device__ __forceinline__ void keys4(const float* __restrict__ u, const float* __restrict__ I,
+                                      int f, const int (&it)[4], double (&acc)[4]) {
+    const float* v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = I + (int64_t)(it[q] >= 0 ? it[q] : 0) * f;
+        acc[q] = 0.0;
+    }
+    int j = 0;
+    if ((f & 1) == 0) {
+        const float2* u2 = (const float2*)u;
+        for (; j + 8 <= f; j += 8) {
+            float2 x[4], y[4][4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = u2[(j >> 1) + e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (it[q] < 0) continue;
+                const float2* v2 = (const float2*)v[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[q][e] = v2[(j >> 1) + e];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (it[q] < 0) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc[q] = __fma_rn((double)x[e].x, (double)y[q][e].x, acc[q]);
+                    acc[q] = __fma_rn((double)x[e].y, (double)y[q][e].y, acc[q]);
+                }
+            }
+        }
+    }
+    for (; j < f; ++j) {
+        const double x = (double)u[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (it[q] >= 0) acc[q] = __fma_rn(x, (double)v[q][j], acc[q]);
+    }
+}
+
 __device__ __forceinline__ void flag_user(const ScreenArgs& a, int64_t u) {
     if (atomicCAS(&a.uflag[u], 0, 1) == 0) {
         unsigned int k = atomicAdd(&a.ctrl->fb_count, 1u);
@@ -157,9 +231,10 @@ __device__ __forceinline__ void list_reset(float (&l)[KM], int K) {
 // each lane's K-th largest entry, and the min over the two lanes of their
 // ceil(K/2)-th largest (together at least K values reach it).
 template <int KM>
-__device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
+__device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx, bool k_is_km) {
     const float t = l[KM - 1];
-    const float th = pick_sorted(l, hidx);
+    // with K == KM (the usual case) the entry's slot is a compile-time index
+    const float th = k_is_km ? l[KM - KM / 2 - 1] : pick_sorted(l, hidx);
     const float tp = xor32_f(t), thp = xor32_f(th);
     return vmax(vmax(t, tp), vmin(th, thp));
 }
@@ -167,6 +242,15 @@ __device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx) {
 // Warm-up sets of per-slot maxima (16 slots per set) used to seed tau.
 __host__ __device__ constexpr int warm_sets(int km) {
     return km <= 16 ? 2 : (km <= 32 ? 3 : 4);
+}
+
+// Certification runs at the end of the screen kernel when the K-list fits a
+// small sorted register list, two user blocks keep every lane busy (one user
+// per lane), and the screen keeps few candidates per user (not E4M3, whose
+// hundreds of candidates per user make one lane per user too slow; there the
+// separate kernel spreads a user over 16 or 64 lanes).
+__host__ __device__ constexpr bool fused_certify(int prec, int km, int ub) {
+    return prec != PREC_FP8 && km <= 16 && ub == 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -196,6 +280,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     int ustop[UB];                // walk: tiles visited before the user stopped
     float lst[UB][KM];
     int cnt[UB], uscale[UB];
+    bool dgn[UB];                 // degenerate user: already on the exact path
     bool act[UB];
     int2* cptr[UB];
 
@@ -292,6 +377,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             flag_user(a, u);
         }
         act[ub] = valid && !degenerate;
+        dgn[ub] = degenerate;
         tau[ub] = ninf;
         cnt[ub] = 0;
         ustop[ub] = -1;
@@ -301,6 +387,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
     const int hidx = KM - (a.K / 2) - 1;
+    const bool k_is_km = a.K == KM;
     const int n_blk = (int)a.n_blk;   // < 2^26 (n_i < 2^31): 32-bit scalar tile arithmetic
     const int* clist = WALK ? a.lists + (int64_t)cluster * a.n_i_pad : nullptr;
     // per-tile bound maxima (prefetched with the tile operands)
@@ -388,7 +475,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             const float ew = fmaf(Au[ub], Cmax, fmaf(Bu[ub], Gmax, slk[ub]));
 #pragma unroll
             for (int q = 0; q < S * 16; ++q) list_insert(lst[ub], gm[ub][q] - ew);
-            tau[ub] = list_tau(lst[ub], hidx);
+            tau[ub] = list_tau(lst[ub], hidx, k_is_km);
             list_reset(lst[ub], a.K);
             tauf[ub] = act[ub] ? tau[ub] : pinf;
         }
@@ -432,7 +519,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         }
                     }
                 }
-                tau[ub] = vmax(tau[ub], list_tau(lst[ub], hidx));
+                tau[ub] = vmax(tau[ub], list_tau(lst[ub], hidx, k_is_km));
                 tauf[ub] = act[ub] ? tau[ub] : pinf;
             }
         }
@@ -493,6 +580,137 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             const float2 mB = bmB;
             load_tile(b + 3 < last ? b + 3 : last, oB, itB, scB, bmB);
             if (!epi_tile(b + 1, acc, eB, mB)) { b_done = b + 2; break; }
+        }
+    }
+
+    // ---- certification in the same wave (short K-lists) ----------------------
+    // Lane 32h + n certifies user n of user block h: it walks the user's two
+    // candidate lists (its own half and the one of lane n + 32 or n), keeps
+    // the pairs whose upper bound reaches tau_u, rescores them in float64,
+    // and keeps the K best by (key desc, index asc) in a sorted register list
+    // (only pairs whose key reaches tau_u can be among them).  The user goes
+    // to the exact path when a list overflowed or fewer than K keys reach
+    // tau_u.  Same rules as certify_kernel, without the round trip through
+    // memory for the per-user state.
+    if constexpr (fused_certify(PREC, KM, UB)) {
+        const int ubl = h;
+        const int x0 = xor32_i(cnt[0]);
+        const int x1 = xor32_i(cnt[UB - 1]);
+        const int cA = (ubl == 1) ? x1 : cnt[0];          // the list of lane n
+        const int cB = (ubl == 1) ? cnt[UB - 1] : x0;     // the list of lane n + 32
+        const float uA = (ubl == 1) ? Au[UB - 1] : Au[0];
+        const float uB = (ubl == 1) ? Bu[UB - 1] : Bu[0];
+        const float us = (ubl == 1) ? slk[UB - 1] : slk[0];
+        const float ut = (ubl == 1) ? tau[UB - 1] : tau[0];
+        const bool ud = (ubl == 1) ? dgn[UB - 1] : dgn[0];
+        bool valid = false;
+        const int64_t u = (h < UB) ? user_of(a, UB, w, ubl, n, tile, &valid) : 0;
+        unsigned long long st_cand = 0, st_resc = 0, st_max = 0;
+        double st_abs = 0.0, st_rel = 0.0;
+        if (valid && !ud) {
+            const int cap = a.cap;
+            const int m0 = cA < cap ? cA : cap, m1 = cB < cap ? cB : cap;
+            bool bad = (cA > cap) || (cB > cap);
+            const int tot = m0 + m1;
+            const int2* list0 = a.cand + (((w * UB + ubl) << 6) + n) * (int64_t)cap;
+            const int2* list1 = a.cand + (((w * UB + ubl) << 6) + n + 32) * (int64_t)cap;
+            const float* urow = a.U + u * a.f;
+            const double tau64 = (double)ut;
+            double unorm = 0.0;
+            if (a.want_stats) {
+                for (int j = 0; j < a.f; ++j) unorm += (double)urow[j] * (double)urow[j];
+                unorm = sqrt(unorm);
+            }
+            double tk[KM];
+            int ti[KM];
+#pragma unroll
+            for (int q = 0; q < KM; ++q) { tk[q] = -__builtin_inf(); ti[q] = 0x7fffffff; }
+            int nkeep = 0;
+            for (int j0 = 0; j0 < tot; j0 += 4) {
+                int2 e[4];
+                float Ci[4], Gi[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = j0 + q;
+                    e[q] = make_int2(0, -1);
+                    if (j < tot) e[q] = (j < m0) ? list0[j] : list1[j - m0];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int item = e[q].y;
+                    Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
+                    Gi[q] = (item >= 0) ? a.Gorig[item] : 0.0f;
+                }
+                int it[4];
+                bool anyk = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float sv = __int_as_float(e[q].x);
+                    const float eb = fmaf(uA, Ci[q], fmaf(uB, Gi[q], us));
+                    it[q] = (e[q].y >= 0 && sv + eb >= ut) ? e[q].y : -1;
+                    anyk = anyk || it[q] >= 0;
+                }
+                if (!anyk) continue;
+                double k4[4];
+                keys4(urow, a.I, a.f, it, k4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (it[q] < 0) continue;
+                    const double key = k4[q];
+                    ++st_resc;
+                    if (a.want_stats) {
+                        const double err = fabs((double)__int_as_float(e[q].x) - key);
+                        st_abs = fmax(st_abs, err);
+                        const double scale = unorm * (double)Ci[q];
+                        if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+                    }
+                    if (key < tau64) continue;   // beaten by K items
+                    ++nkeep;
+                    // insert into the sorted list: every slot from the old list
+                    const int ix = it[q];
+#pragma unroll
+                    for (int q2 = KM - 1; q2 >= 1; --q2) {
+                        const bool above = before(key, ix, tk[q2 - 1], ti[q2 - 1]);
+                        const bool here = before(key, ix, tk[q2], ti[q2]);
+                        const double nk = above ? tk[q2 - 1] : (here ? key : tk[q2]);
+                        const int ni = above ? ti[q2 - 1] : (here ? ix : ti[q2]);
+                        tk[q2] = nk;
+                        ti[q2] = ni;
+                    }
+                    if (before(key, ix, tk[0], ti[0])) { tk[0] = key; ti[0] = ix; }
+                }
+            }
+            st_cand = (unsigned long long)(cA + cB);
+            st_max = st_cand;
+            if (bad || nkeep < a.K) {
+                flag_user(a, u);
+            } else {
+#pragma unroll
+                for (int q = 0; q < KM; ++q) {
+                    if (q < a.K) {
+                        a.out_idx[u * a.K + q] = ti[q];
+                        a.out_score[u * a.K + q] = tk[q];
+                    }
+                }
+            }
+        } else if (valid) {
+            st_max = (unsigned long long)(cA + cB);
+        }
+        if (a.want_stats) {
+            for (int off = 32; off >= 1; off >>= 1) {
+                st_cand += __shfl_xor(st_cand, off);
+                st_resc += __shfl_xor(st_resc, off);
+                st_max = max(st_max, (unsigned long long)__shfl_xor(st_max, off));
+                st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
+                st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
+            }
+            if (lane == 0) {
+                if (st_cand) atomicAdd(&a.ctrl->cand_total, st_cand);
+                if (st_resc) atomicAdd(&a.ctrl->rescored, st_resc);
+                if (st_max) atomicMax(&a.ctrl->cand_max, st_max);
+                atomic_max_nonneg((double*)&a.ctrl->max_abs_err, st_abs);
+                atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
+            }
         }
     }
 
