@@ -15,11 +15,13 @@ enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
 
 // User blocks of 32 per screen wave.  Each user block holds its operand
 // registers, two accumulator sets (software pipeline) and a KM-entry K-list,
-// so fewer blocks fit when the list or the operands grow.
+// so fewer blocks fit when the list or the operands grow: two blocks up to a
+// 32-entry list, except for the float32 screen past 16 entries or 32 chunks
+// and the bfloat16 screen with a 32-entry list over 8 chunks.
 __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap) {
     return prec == PREC_FP32
                ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
-               : ((prec == PREC_BF16 && nch_cap >= 8) ? 1 : (km <= 32 ? 2 : 1));
+               : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1));
 }
 
 // Device-resident control block of one call.  Zeroed at the start of every
