@@ -1,6 +1,8 @@
 // Certification of the screen's candidates with a float64 rescore, the exact
 // float64 fallback, and the screen launch dispatcher.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "screen_core.h"
 
@@ -162,6 +164,233 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
         if (st_cand) atomicAdd(&a.ctrl->cand_total, st_cand);
         if (st_resc) atomicAdd(&a.ctrl->rescored, st_resc);
         if (st_max) atomicMax(&a.ctrl->cand_max, st_max);
+        atomic_max_nonneg((double*)&a.ctrl->max_abs_err, st_abs);
+        atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Certification with one wave per user, for screens that keep hundreds of
+// candidates per user (E4M3).  The candidates whose upper bound reaches the
+// threshold are rescored 64 at a time: their item rows are staged through LDS
+// in blocks of 32 factors with coalesced loads (whole cache lines rather than
+// one scattered 8-byte load per lane), and lane r continues the left-to-right
+// float64 sum of row r.  After each block of 64 rescored pairs the K-th
+// largest key seen so far replaces tau_u when larger (it is the K-th largest
+// key of a subset, so still at most the user's K-th largest key), which
+// removes most later candidates before their rows are read.  Kept pairs
+// (key >= threshold) stay in LDS, pruned to the threshold after each block.
+// ---------------------------------------------------------------------------
+constexpr int kCwCols = 32;      // factors per staged block
+constexpr int kCwKeys = 256;     // kept pairs per user (more: exact fallback)
+
+template <int VEC>
+__global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, int UB, int64_t n_ublk) {
+    typedef float __attribute__((ext_vector_type(VEC))) vec_t;
+    constexpr int NV = kCwCols / VEC;          // vectors per row and block
+    constexpr int LOADS = 64 * NV / 64;        // vector loads per lane and block
+    __shared__ double su[256];
+    __shared__ int2 pend[128];
+    __shared__ __attribute__((aligned(16))) float stage[64][kCwCols + 4];
+    __shared__ double skey[kCwKeys];
+    __shared__ int sidx[kCwKeys];
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t ublk = (int64_t)blockIdx.x >> 5;
+    const int n = (int)(blockIdx.x & 31);
+    if (ublk >= n_ublk) return;
+    const int64_t w = ublk / UB;
+    const int ub = (int)(ublk - w * UB);
+    int4 tile = make_int4(0, 0, 0, 0);
+    if (a.walk) tile = a.tiles[w];
+    bool valid;
+    const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
+    if (!valid) return;
+    const int c0 = a.cnt[(ublk << 6) + n], c1 = a.cnt[(ublk << 6) + n + 32];
+    const bool flagged = a.uflag[u] != 0;
+    const bool over = c0 > a.cap || c1 > a.cap;
+    if (flagged || over) {
+        if (lane == 0) {
+            if (!flagged) flag_user(a, u);
+            if (a.want_stats) {
+                if (!flagged) atomicAdd(&a.ctrl->cand_total, (unsigned long long)(c0 + c1));
+                atomicMax(&a.ctrl->cand_max, (unsigned long long)(c0 + c1));
+            }
+        }
+        return;
+    }
+    const int f = a.f, K = a.K;
+    const float* urow = a.U + u * f;
+    for (int j = lane; j < f; j += 64) su[j] = (double)urow[j];
+    const float4 us = a.uscal[u];
+    double tau64 = (double)us.w;       // kept pairs: key >= tau64
+    float thr = us.w;                  // candidates: upper bound >= thr (thr <= tau64)
+    const int tot = c0 + c1;
+    const int2* list0 = a.cand + ((ublk << 6) + n) * (int64_t)a.cap;
+    const int2* list1 = a.cand + ((ublk << 6) + n + 32) * (int64_t)a.cap;
+    __syncthreads();
+    double unorm = 0.0;   // ||u||, for the relative error statistic only
+    if (a.want_stats) {
+        for (int j = 0; j < f; ++j) unorm += su[j] * su[j];
+        unorm = sqrt(unorm);
+    }
+    int npend = 0, nk = 0, rescored = 0;
+    bool lost = false;                 // more than kCwKeys kept pairs
+    double st_abs = 0.0, st_rel = 0.0;
+
+    // Rescore pend[0 .. nr): stage the rows, sum, keep keys >= tau64, then
+    // raise tau64 / thr to the K-th largest kept key and prune the kept set.
+    auto rescore = [&](int nr) __attribute__((always_inline)) {
+        const float* rowp[LOADS];
+        int col[LOADS];
+#pragma unroll
+        for (int s = 0; s < LOADS; ++s) {
+            const int e = s * 64 + lane, r = e / NV;
+            col[s] = (e - r * NV) * VEC;
+            rowp[s] = (r < nr) ? a.I + (int64_t)pend[r].y * f : nullptr;
+        }
+        vec_t v[LOADS];
+        auto load = [&](int j0) __attribute__((always_inline)) {
+#pragma unroll
+            for (int s = 0; s < LOADS; ++s) {
+                const int c = j0 + col[s];
+                if (rowp[s] && c < f) v[s] = *(const vec_t*)(rowp[s] + c);
+            }
+        };
+        load(0);
+        double acc = 0.0;
+        for (int j0 = 0; j0 < f; j0 += kCwCols) {
+            __syncthreads();   // the previous block's sums have read the stage
+#pragma unroll
+            for (int s = 0; s < LOADS; ++s) {
+                const int e = s * 64 + lane, r = e / NV;
+                if (rowp[s] && j0 + col[s] < f) *(vec_t*)&stage[r][col[s]] = v[s];
+            }
+            __syncthreads();
+            if (j0 + kCwCols < f) load(j0 + kCwCols);
+            const int nc = min(kCwCols, f - j0);
+            if (lane < nr) {
+                if (nc == kCwCols) {
+#pragma unroll
+                    for (int c = 0; c < kCwCols; ++c)
+                        acc = __fma_rn(su[j0 + c], (double)stage[lane][c], acc);
+                } else {
+                    for (int c = 0; c < nc; ++c)
+                        acc = __fma_rn(su[j0 + c], (double)stage[lane][c], acc);
+                }
+            }
+        }
+        const bool has = lane < nr;
+        const int2 ent = has ? pend[lane] : make_int2(0, -1);
+        if (has && a.want_stats) {
+            const double err = fabs((double)__int_as_float(ent.x) - acc);
+            st_abs = fmax(st_abs, err);
+            const double scale = unorm * (double)a.Corig[ent.y];
+            if (scale > 0.0) st_rel = fmax(st_rel, err / scale);
+        }
+        rescored += nr;
+        const bool take = has && acc >= tau64;
+        const uint64_t bt = ballot(take);
+        const int pos = nk + __builtin_popcountll(bt & below);
+        if (take && pos < kCwKeys) { skey[pos] = acc; sidx[pos] = ent.y; }
+        nk += __builtin_popcountll(bt);
+        if (nk > kCwKeys) { lost = true; nk = kCwKeys; }
+        __syncthreads();
+        if (nk < K || lost) return;
+        // K-th largest kept key: the entry with fewer than K keys above it
+        // and at least K at or above it
+        double kth = -__builtin_inf();
+        for (int x = lane; x < nk; x += 64) {
+            const double kx = skey[x];
+            int gt = 0, ge = 0;
+            for (int y = 0; y < nk; ++y) {
+                const double ky = skey[y];
+                gt += ky > kx ? 1 : 0;
+                ge += ky >= kx ? 1 : 0;
+            }
+            if (gt < K && ge >= K) kth = kx;
+        }
+        for (int off = 32; off >= 1; off >>= 1) kth = fmax(kth, __shfl_xor(kth, off));
+        if (kth > tau64) {
+            tau64 = kth;
+            thr = fmaxf(thr, __double2float_rd(kth));
+        }
+        // drop kept pairs below the raised threshold
+        double kk[kCwKeys / 64];
+        int ki[kCwKeys / 64];
+        bool kp[kCwKeys / 64];
+#pragma unroll
+        for (int q = 0; q < kCwKeys / 64; ++q) {
+            const int x = q * 64 + lane;
+            kp[q] = x < nk && skey[x] >= tau64;
+            kk[q] = kp[q] ? skey[x] : 0.0;
+            ki[q] = kp[q] ? sidx[x] : 0;
+        }
+        __syncthreads();
+        int m = 0;
+#pragma unroll
+        for (int q = 0; q < kCwKeys / 64; ++q) {
+            const uint64_t bq = ballot(kp[q]);
+            if (kp[q]) {
+                const int p2 = m + __builtin_popcountll(bq & below);
+                skey[p2] = kk[q];
+                sidx[p2] = ki[q];
+            }
+            m += __builtin_popcountll(bq);
+        }
+        nk = m;
+        __syncthreads();
+    };
+
+    for (int base = 0; base < tot; base += 64) {
+        const int j = base + lane;
+        int2 e = make_int2(0, -1);
+        if (j < tot) e = (j < c0) ? list0[j] : list1[j - c0];
+        bool keep = false;
+        if (e.y >= 0) {
+            const float eb = fmaf(us.x, a.Corig[e.y], fmaf(us.y, a.Gorig[e.y], us.z));
+            keep = __int_as_float(e.x) + eb >= thr;
+        }
+        const uint64_t bk = ballot(keep);
+        if (keep) pend[npend + __builtin_popcountll(bk & below)] = e;
+        npend += __builtin_popcountll(bk);
+        if (npend >= 64) {
+            __syncthreads();
+            rescore(64);
+            const int rest = npend - 64;
+            const int2 t = (lane < rest) ? pend[64 + lane] : make_int2(0, -1);
+            __syncthreads();
+            if (lane < rest) pend[lane] = t;
+            npend = rest;
+        }
+    }
+    if (npend > 0) {
+        __syncthreads();
+        rescore(npend);
+    }
+    if (lost || nk < K) {
+        if (lane == 0) flag_user(a, u);
+    } else {
+        for (int x = lane; x < nk; x += 64) {
+            const double kx = skey[x];
+            const int ix = sidx[x];
+            int rank = 0;
+            for (int y = 0; y < nk; ++y) rank += before(skey[y], sidx[y], kx, ix) ? 1 : 0;
+            if (rank < K) {
+                a.out_idx[u * K + rank] = ix;
+                a.out_score[u * K + rank] = kx;
+            }
+        }
+    }
+    if (!a.want_stats) return;
+    for (int off = 32; off >= 1; off >>= 1) {
+        st_abs = fmax(st_abs, __shfl_xor(st_abs, off));
+        st_rel = fmax(st_rel, __shfl_xor(st_rel, off));
+    }
+    if (lane == 0) {
+        atomicAdd(&a.ctrl->cand_total, (unsigned long long)tot);
+        atomicMax(&a.ctrl->cand_max, (unsigned long long)tot);
+        if (rescored) atomicAdd(&a.ctrl->rescored, (unsigned long long)rescored);
         atomic_max_nonneg((double*)&a.ctrl->max_abs_err, st_abs);
         atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
     }
@@ -349,6 +578,24 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 // Per-user bin of kept candidates in certification (LDS).
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     if (fused_certify(p.prec, p.KM, p.UB)) return hipSuccess;   // done by the screen kernel
+    // one wave per user for E4M3's long candidate lists (MIPS_DEBUG_CERTIFY
+    // = "wave" or "group" forces either kernel, for tests)
+    bool wave = p.prec == PREC_FP8;
+    if (const char* env = std::getenv("MIPS_DEBUG_CERTIFY")) {
+        if (std::strcmp(env, "wave") == 0) wave = true;
+        if (std::strcmp(env, "group") == 0) wave = false;
+    }
+    if (wave) {
+        const uintptr_t base = (uintptr_t)a.I;
+        const dim3 grid((unsigned)(p.n_ublk * 32)), blk(64);
+        if (p.f % 4 == 0 && base % 16 == 0)
+            certify_wave_kernel<4><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        else if (p.f % 2 == 0 && base % 8 == 0)
+            certify_wave_kernel<2><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        else
+            certify_wave_kernel<1><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        return hipGetLastError();
+    }
     // lanes per user G and LDS slots per lane EM (pairs whose key reaches
     // tau_u): 64 per user for the float32/bfloat16 screens at K <= 16, 256
     // for larger K or E4M3 at K <= 16, 1024 for E4M3 at larger K

@@ -82,6 +82,19 @@ def test_query_small_all_users(prec, C, K):
         assert st["mean_items_visited"] < 0.5 * I.shape[0]
 
 
+@pytest.mark.parametrize("mode", ["wave", "group"])
+@pytest.mark.parametrize("prec,K", [("fp32", 32), ("bf16", 50), ("fp8", 10)])
+def test_query_certification_kernels(mode, prec, K, monkeypatch):
+    """The walk's candidates certified by either certification kernel."""
+    log(f"maximus certify {mode} prec={prec} K={K}")
+    U, I = mipsgen.generate("clustered", 5, n_users=3000, n_items=2500, f=50)
+    ix = _build(U, I, 16)
+    monkeypatch.setenv("MIPS_DEBUG_CERTIFY", mode)
+    idx, score = _query(ix, K, prec)
+    monkeypatch.delenv("MIPS_DEBUG_CERTIFY")
+    assert_parity(idx, score, U, I, K)
+
+
 def test_singleton_clusters_and_degenerate_rows():
     U, I = mipsgen.generate("mf", 3, n_users=300, n_items=900, f=20)
     U[5] = 0.0
