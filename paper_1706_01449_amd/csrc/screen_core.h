@@ -615,7 +615,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             const int2* list0 = a.cand + (((w * UB + ubl) << 6) + n) * (int64_t)cap;
             const int2* list1 = a.cand + (((w * UB + ubl) << 6) + n + 32) * (int64_t)cap;
             const float* urow = a.U + u * a.f;
-            const double tau64 = (double)ut;
+            double tau64 = (double)ut;   // kept pairs: key >= tau64
+            float thr = ut;              // rescored pairs: upper bound >= thr (<= tau64)
             double unorm = 0.0;
             if (a.want_stats) {
                 for (int j = 0; j < a.f; ++j) unorm += (double)urow[j] * (double)urow[j];
@@ -647,7 +648,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 for (int q = 0; q < 4; ++q) {
                     const float sv = __int_as_float(e[q].x);
                     const float eb = fmaf(uA, Ci[q], fmaf(uB, Gi[q], us));
-                    it[q] = (e[q].y >= 0 && sv + eb >= ut) ? e[q].y : -1;
+                    it[q] = (e[q].y >= 0 && sv + eb >= thr) ? e[q].y : -1;
                     anyk = anyk || it[q] >= 0;
                 }
                 if (!anyk) continue;
@@ -678,6 +679,21 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         ti[q2] = ni;
                     }
                     if (before(key, ix, tk[0], ti[0])) { tk[0] = key; ti[0] = ix; }
+                }
+                // once K keys are kept, the K-th largest of them is at most
+                // the user's K-th largest key: later pairs below it need no
+                // rescore
+                if (nkeep >= a.K) {
+                    double kth = tk[KM - 1];
+                    if (!k_is_km) {
+#pragma unroll
+                        for (int q = 0; q < KM; ++q)
+                            if (q == a.K - 1) kth = tk[q];
+                    }
+                    if (kth > tau64) {
+                        tau64 = kth;
+                        thr = fmaxf(thr, __double2float_rd(kth));
+                    }
                 }
             }
             st_cand = (unsigned long long)(cA + cB);
