@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
 // Certification with one wave per user, for screens that keep hundreds of
 // candidates per user (E4M3).  The candidates whose upper bound reaches the
 // threshold are rescored 64 at a time: their item rows are staged through LDS
-// in blocks of 32 factors with coalesced loads (whole cache lines rather than
+// in blocks of 16 factors with coalesced loads (64-byte row segments rather than
 // one scattered 8-byte load per lane), and lane r continues the left-to-right
 // float64 sum of row r.  After each block of 64 rescored pairs the K-th
 // largest key seen so far replaces tau_u when larger (it is the K-th largest
@@ -181,8 +181,8 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
 // removes most later candidates before their rows are read.  Kept pairs
 // (key >= threshold) stay in LDS, pruned to the threshold after each block.
 // ---------------------------------------------------------------------------
-constexpr int kCwCols = 32;      // factors per staged block
-constexpr int kCwKeys = 256;     // kept pairs per user (more: exact fallback)
+constexpr int kCwCols = 16;      // factors per staged block
+constexpr int kCwKeys = 128;     // kept pairs per user (more: exact fallback)
 
 template <int VEC>
 __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, int UB, int64_t n_ublk) {
@@ -578,9 +578,10 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 // Per-user bin of kept candidates in certification (LDS).
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     if (fused_certify(p.prec, p.KM, p.UB)) return hipSuccess;   // done by the screen kernel
-    // one wave per user for E4M3's long candidate lists (MIPS_DEBUG_CERTIFY
-    // = "wave" or "group" forces either kernel, for tests)
-    bool wave = p.prec == PREC_FP8;
+    // one wave per user for long candidate lists (E4M3, or K > 16), a group
+    // of lanes per user for short ones (MIPS_DEBUG_CERTIFY = "wave" or
+    // "group" forces either kernel, for tests)
+    bool wave = p.prec == PREC_FP8 || p.K > 16;
     if (const char* env = std::getenv("MIPS_DEBUG_CERTIFY")) {
         if (std::strcmp(env, "wave") == 0) wave = true;
         if (std::strcmp(env, "group") == 0) wave = false;
