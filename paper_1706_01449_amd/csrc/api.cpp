@@ -75,6 +75,11 @@ PhaseTimer::~PhaseTimer() {
 // ---------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool cascade_enabled() {
+    const char* env = std::getenv("MIPS_CERTIFY_CASCADE");
+    return env && std::strcmp(env, "1") == 0;
+}
+
 bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t, ScreenPlan* out) {
     ScreenPlan p;
     p.prec = prec;
@@ -130,18 +135,24 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
 }
 
 struct BmmLayout {
-    size_t ctrl, hist, uflag, zero_end;
+    size_t ctrl, ctrlb, hist, uflag, zero_end;
     size_t flist, uscal, bucket, perm, Corig, Gorig, Eorig, kexp, qrow, packed, pscale, blockmax,
         tailmax;
+    size_t qrowb, Gorigb, Eorigb;   // bfloat16 rows of the E4M3 certification cascade
     size_t cnt, cand, fbkeys, total;
 };
+
+// bfloat16 row stride of the cascade: f rounded up to 8 (16-byte rows)
+static int cascade_stride(int f) { return (f + 7) & ~7; }
 
 static BmmLayout bmm_layout(const ScreenPlan& p) {
     BmmLayout L{};
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += al256(b); return r; };
     const size_t esz = p.prec == PREC_FP32 ? 4 : (p.prec == PREC_BF16 ? 2 : 1);
+    const bool casc = p.fast && p.prec == PREC_FP8;
     L.ctrl = take(sizeof(Ctrl));
+    L.ctrlb = take(sizeof(Ctrl));
     L.hist = take(2 * kBuckets * sizeof(unsigned int));
     L.uflag = take((size_t)p.n_u * 4);
     L.zero_end = o;
@@ -159,6 +170,11 @@ static BmmLayout bmm_layout(const ScreenPlan& p) {
         L.pscale = take((size_t)p.n_i_pad * 4);
         L.blockmax = take((size_t)p.n_blk * 8);
         L.tailmax = take((size_t)p.n_blk * 4);
+        if (casc) {
+            L.qrowb = take((size_t)p.n_i * cascade_stride(p.f) * 2);
+            L.Gorigb = take((size_t)p.n_i * 4);
+            L.Eorigb = take((size_t)p.n_i * 4);
+        }
         L.cnt = take((size_t)p.n_ublk * 64 * 4);
         L.cand = take((size_t)p.n_ublk * p.cap * 64 * 8);
     }
@@ -325,6 +341,25 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
             ia.ctrl = ctrl;
             if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
                 return hip_fail(e, "item preparation");
+            if (precision == PREC_FP8 && cascade_enabled()) {
+                // bfloat16 rows and residual norms for the certification cascade
+                ItemPrepArgs ib{};
+                ib.I = I;
+                ib.n_i = n_i;
+                ib.n_blk = p.n_blk;
+                ib.f = f;
+                ib.f_pad = cascade_stride(f);
+                ib.nch = p.nch;
+                const double n = (double)ib.f_pad;
+                ib.gamma = (float)(n * 0x1p-22 / (1.0 - n * 0x1p-22) * (1.0 + 0x1p-20));
+                ib.Corig = (float*)(ws + L.Corig);   // the same rounded-up norms
+                ib.Gorig = (float*)(ws + L.Gorigb);
+                ib.Eorig = (float*)(ws + L.Eorigb);
+                ib.qrow = ws + L.qrowb;
+                ib.ctrl = (Ctrl*)(ws + L.ctrlb);
+                if ((e = launch_item_prep(PREC_BF16, ib, false, s)) != hipSuccess)
+                    return hip_fail(e, "cascade rows");
+            }
             if (prune &&
                 (e = launch_tailmax(ia.blockmax, p.n_blk, (float*)(ws + L.tailmax), s)) != hipSuccess)
                 return hip_fail(e, "tile norm maxima");
@@ -366,6 +401,12 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
         a.kexp = (const int*)(ws + L.kexp);
         a.Corig = (const float*)(ws + L.Corig);
         a.Gorig = (const float*)(ws + L.Gorig);
+        if (precision == PREC_FP8 && cascade_enabled()) {
+            a.qrow_b = ws + L.qrowb;
+            a.Gorig_b = (const float*)(ws + L.Gorigb);
+            a.maxb = &((const Ctrl*)(ws + L.ctrlb))->cmax_bits;
+            a.fpb = cascade_stride(f);
+        }
         a.n_ublk = p.n_ublk;
         a.cnt = (int*)(ws + L.cnt);
         a.cand = (int2*)(ws + L.cand);

@@ -170,30 +170,42 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
 }
 
 // ---------------------------------------------------------------------------
-// Certification with one wave per user, for screens that keep hundreds of
-// candidates per user (E4M3).  The candidates whose upper bound reaches the
-// threshold are rescored 64 at a time: their item rows are staged through LDS
-// in blocks of 16 factors with coalesced loads (64-byte row segments rather than
-// one scattered 8-byte load per lane), and lane r continues the left-to-right
+// Certification with one wave per user, for long candidate lists (E4M3, or
+// K > 16).  The candidates whose upper bound reaches the threshold are
+// rescored 64 at a time: their item rows are staged through LDS in blocks of
+// 16 factors with coalesced loads (64-byte row segments rather than one
+// scattered 8-byte load per lane), and lane r continues the left-to-right
 // float64 sum of row r.  After each block of 64 rescored pairs the K-th
 // largest key seen so far replaces tau_u when larger (it is the K-th largest
 // key of a subset, so still at most the user's K-th largest key), which
 // removes most later candidates before their rows are read.  Kept pairs
 // (key >= threshold) stay in LDS, pruned to the threshold after each block.
+//
+// Cascade (CASC, E4M3 screens): before the float64 rescore, each block of 64
+// surviving candidates is re-screened with bfloat16 copies of the user and
+// item rows (float32 sum, the screen's error bound with bfloat16 residual
+// norms).  The K-th largest bfloat16 lower bound also raises the threshold,
+// and only pairs whose bfloat16 upper bound reaches it are rescored, which
+// reads 2-byte instead of 4-byte factors for most of the E4M3 candidates.
 // ---------------------------------------------------------------------------
 constexpr int kCwCols = 16;      // factors per staged block
 constexpr int kCwKeys = 128;     // kept pairs per user (more: exact fallback)
 
-template <int VEC>
+template <int VEC, bool CASC>
 __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, int UB, int64_t n_ublk) {
     typedef float __attribute__((ext_vector_type(VEC))) vec_t;
     constexpr int NV = kCwCols / VEC;          // vectors per row and block
     constexpr int LOADS = 64 * NV / 64;        // vector loads per lane and block
+    constexpr int CB = 2 * kCwCols;            // bfloat16 factors per staged block
+    constexpr int LB = CB / 8;                 // 16-byte loads per lane and block (bfloat16)
     __shared__ double su[256];
-    __shared__ int2 pend[128];
+    __shared__ float sub[CASC ? 256 : 1];      // bfloat16 copy of u (as floats)
+    __shared__ int2 pend[128];                 // candidates passing the screen's bound
+    __shared__ int2 pend2[CASC ? 128 : 1];     // ... and the bfloat16 bound
     __shared__ __attribute__((aligned(16))) float stage[64][kCwCols + 4];
     __shared__ double skey[kCwKeys];
     __shared__ int sidx[kCwKeys];
+    __shared__ double slb[CASC ? kCwKeys : 1]; // bfloat16 lower bounds >= threshold
     const int lane = threadIdx.x;
     const uint64_t below = (1ull << lane) - 1ull;
     const int64_t ublk = (int64_t)blockIdx.x >> 5;
@@ -222,6 +234,33 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     const int f = a.f, K = a.K;
     const float* urow = a.U + u * f;
     for (int j = lane; j < f; j += 64) su[j] = (double)urow[j];
+    // bfloat16 re-screen bound of this user (as in the screen's prologue)
+    float Ab = 0.0f, Bb = 0.0f, Sb = 0.0f;
+    if (CASC) {
+        double s2 = 0.0, r2 = 0.0, q2 = 0.0;
+        for (int j = lane; j < a.fpb; j += 64) {
+            const float x = j < f ? urow[j] : 0.0f;
+            const float d = bf16_bits_to_f32(f32_to_bf16_bits(x));
+            s2 += (double)x * (double)x;
+            r2 += ((double)x - (double)d) * ((double)x - (double)d);
+            q2 += (double)d * (double)d;
+            sub[j] = d;
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            s2 += __shfl_xor(s2, off);
+            r2 += __shfl_xor(r2, off);
+            q2 += __shfl_xor(q2, off);
+        }
+        const double N64 = sqrt(s2);
+        Ab = norm_up_f32(sqrt(r2) + (double)f * 0x1p-52 * N64);
+        Bb = norm_up_f32(sqrt(q2));
+        const double Cmax = (double)__uint_as_float(a.maxb[0]);
+        const double Emax = (double)__uint_as_float(a.maxb[1]);
+        const double Gmax = (double)__uint_as_float(a.maxb[2]);
+        const double M = N64 * Cmax * 1.01 + (double)Bb * Emax * 1.01 + (double)Ab * Cmax +
+                         (double)Bb * Gmax;
+        Sb = round_up_f32(M * 0x1p-20 + 0x1p-100);
+    }
     const float4 us = a.uscal[u];
     double tau64 = (double)us.w;       // kept pairs: key >= tau64
     float thr = us.w;                  // candidates: upper bound >= thr (thr <= tau64)
@@ -234,20 +273,66 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
         for (int j = 0; j < f; ++j) unorm += su[j] * su[j];
         unorm = sqrt(unorm);
     }
-    int npend = 0, nk = 0, rescored = 0;
+    int npend = 0, npend2 = 0, nk = 0, nlb = 0, rescored = 0;
     bool lost = false;                 // more than kCwKeys kept pairs
     double st_abs = 0.0, st_rel = 0.0;
 
-    // Rescore pend[0 .. nr): stage the rows, sum, keep keys >= tau64, then
-    // raise tau64 / thr to the K-th largest kept key and prune the kept set.
-    auto rescore = [&](int nr) __attribute__((always_inline)) {
+    // K-th largest of v[0 .. m) (-inf when m < K): the entry with fewer than
+    // K values above it and at least K at or above it.
+    auto kth_of = [&](const double* v, int m) __attribute__((always_inline)) {
+        double kth = -__builtin_inf();
+        if (m < K) return kth;
+        for (int x = lane; x < m; x += 64) {
+            const double vx = v[x];
+            int gt = 0, ge = 0;
+            for (int y = 0; y < m; ++y) {
+                const double vy = v[y];
+                gt += vy > vx ? 1 : 0;
+                ge += vy >= vx ? 1 : 0;
+            }
+            if (gt < K && ge >= K) kth = vx;
+        }
+        for (int off = 32; off >= 1; off >>= 1) kth = fmax(kth, __shfl_xor(kth, off));
+        return kth;
+    };
+    // drop the entries of v (and of ix, when given) below t; returns the count left
+    auto prune = [&](double* v, int* ix, int m, double t) __attribute__((always_inline)) {
+        double kv[kCwKeys / 64];
+        int ki[kCwKeys / 64];
+        bool kp[kCwKeys / 64];
+#pragma unroll
+        for (int q = 0; q < kCwKeys / 64; ++q) {
+            const int x = q * 64 + lane;
+            kp[q] = x < m && v[x] >= t;
+            kv[q] = kp[q] ? v[x] : 0.0;
+            ki[q] = (kp[q] && ix) ? ix[x] : 0;
+        }
+        __syncthreads();
+        int r = 0;
+#pragma unroll
+        for (int q = 0; q < kCwKeys / 64; ++q) {
+            const uint64_t bq = ballot(kp[q]);
+            if (kp[q]) {
+                const int p2 = r + __builtin_popcountll(bq & below);
+                v[p2] = kv[q];
+                if (ix) ix[p2] = ki[q];
+            }
+            r += __builtin_popcountll(bq);
+        }
+        __syncthreads();
+        return r;
+    };
+
+    // Rescore src[0 .. nr) in float64: stage the rows, sum, keep keys >=
+    // tau64, then raise tau64 / thr to the K-th largest kept key and prune.
+    auto rescore = [&](const int2* src, int nr) __attribute__((always_inline)) {
         const float* rowp[LOADS];
         int col[LOADS];
 #pragma unroll
         for (int s = 0; s < LOADS; ++s) {
             const int e = s * 64 + lane, r = e / NV;
             col[s] = (e - r * NV) * VEC;
-            rowp[s] = (r < nr) ? a.I + (int64_t)pend[r].y * f : nullptr;
+            rowp[s] = (r < nr) ? a.I + (int64_t)src[r].y * f : nullptr;
         }
         vec_t v[LOADS];
         auto load = [&](int j0) __attribute__((always_inline)) {
@@ -281,7 +366,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
             }
         }
         const bool has = lane < nr;
-        const int2 ent = has ? pend[lane] : make_int2(0, -1);
+        const int2 ent = has ? src[lane] : make_int2(0, -1);
         if (has && a.want_stats) {
             const double err = fabs((double)__int_as_float(ent.x) - acc);
             st_abs = fmax(st_abs, err);
@@ -297,49 +382,92 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
         if (nk > kCwKeys) { lost = true; nk = kCwKeys; }
         __syncthreads();
         if (nk < K || lost) return;
-        // K-th largest kept key: the entry with fewer than K keys above it
-        // and at least K at or above it
-        double kth = -__builtin_inf();
-        for (int x = lane; x < nk; x += 64) {
-            const double kx = skey[x];
-            int gt = 0, ge = 0;
-            for (int y = 0; y < nk; ++y) {
-                const double ky = skey[y];
-                gt += ky > kx ? 1 : 0;
-                ge += ky >= kx ? 1 : 0;
-            }
-            if (gt < K && ge >= K) kth = kx;
-        }
-        for (int off = 32; off >= 1; off >>= 1) kth = fmax(kth, __shfl_xor(kth, off));
+        const double kth = kth_of(skey, nk);
         if (kth > tau64) {
             tau64 = kth;
             thr = fmaxf(thr, __double2float_rd(kth));
         }
-        // drop kept pairs below the raised threshold
-        double kk[kCwKeys / 64];
-        int ki[kCwKeys / 64];
-        bool kp[kCwKeys / 64];
+        nk = prune(skey, sidx, nk, tau64);
+    };
+
+    // bfloat16 re-screen of pend[0 .. nr) into pend2 (CASC only).
+    auto cascade = [&](int nr) __attribute__((always_inline)) {
+        const uint16_t* rowb[LB];
+        int colb[LB];
 #pragma unroll
-        for (int q = 0; q < kCwKeys / 64; ++q) {
-            const int x = q * 64 + lane;
-            kp[q] = x < nk && skey[x] >= tau64;
-            kk[q] = kp[q] ? skey[x] : 0.0;
-            ki[q] = kp[q] ? sidx[x] : 0;
+        for (int s = 0; s < LB; ++s) {
+            const int e = s * 64 + lane, r = e / (CB / 8);
+            colb[s] = (e - r * (CB / 8)) * 8;
+            rowb[s] = (r < nr) ? (const uint16_t*)a.qrow_b + (int64_t)pend[r].y * a.fpb : nullptr;
         }
-        __syncthreads();
-        int m = 0;
+        float acc = 0.0f;
+        for (int j0 = 0; j0 < a.fpb; j0 += CB) {
+            intx4_t v[LB];
 #pragma unroll
-        for (int q = 0; q < kCwKeys / 64; ++q) {
-            const uint64_t bq = ballot(kp[q]);
-            if (kp[q]) {
-                const int p2 = m + __builtin_popcountll(bq & below);
-                skey[p2] = kk[q];
-                sidx[p2] = ki[q];
+            for (int s = 0; s < LB; ++s)
+                if (rowb[s] && j0 + colb[s] < a.fpb) v[s] = *(const intx4_t*)(rowb[s] + j0 + colb[s]);
+            __syncthreads();   // the previous block's sums have read the stage
+#pragma unroll
+            for (int s = 0; s < LB; ++s) {
+                const int e = s * 64 + lane, r = e / (CB / 8);
+                if (rowb[s] && j0 + colb[s] < a.fpb) *(intx4_t*)&stage[r][colb[s] / 2] = v[s];
             }
-            m += __builtin_popcountll(bq);
+            __syncthreads();
+            const int nc = min(CB, a.fpb - j0);
+            if (lane < nr) {
+                if (nc == CB) {
+                    const intx4_t* rs4 = (const intx4_t*)&stage[lane][0];
+#pragma unroll
+                    for (int q = 0; q < CB / 8; ++q) {
+                        const intx4_t wv = rs4[q];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const uint32_t wd = (uint32_t)wv[t];
+                            acc = fmaf(sub[j0 + 8 * q + 2 * t], __uint_as_float(wd << 16), acc);
+                            acc = fmaf(sub[j0 + 8 * q + 2 * t + 1], __uint_as_float(wd & 0xffff0000u), acc);
+                        }
+                    }
+                } else {
+                    const uint16_t* rs = (const uint16_t*)&stage[lane][0];
+                    for (int c = 0; c < nc; ++c) acc = fmaf(sub[j0 + c], bf16_bits_to_f32(rs[c]), acc);
+                }
+            }
         }
-        nk = m;
+        const bool has = lane < nr;
+        const int2 ent = has ? pend[lane] : make_int2(0, -1);
+        float lb = -__builtin_inff(), ubd = -__builtin_inff();
+        if (has) {
+            const float e = fmaf(Ab, a.Corig[ent.y], fmaf(Bb, a.Gorig_b[ent.y], Sb));
+            lb = acc - e;
+            ubd = acc + e;
+        }
+        // lower bounds of distinct items: their K-th largest raises thr
+        const bool tl = has && lb >= thr;
+        const uint64_t bl = ballot(tl);
+        const int pl = nlb + __builtin_popcountll(bl & below);
+        if (tl && pl < kCwKeys) slb[pl] = (double)lb;
+        nlb = min(kCwKeys, nlb + __builtin_popcountll(bl));   // a subset still bounds
         __syncthreads();
+        const double kl = kth_of(slb, nlb);
+        if (kl > (double)thr) {
+            thr = (float)kl;   // a float32 lower bound: exact
+            tau64 = fmax(tau64, kl);
+        }
+        if (nlb >= K) nlb = prune(slb, nullptr, nlb, (double)thr);
+        // pairs whose bfloat16 upper bound reaches thr go to the rescore
+        const bool pass = has && ubd >= thr;
+        const uint64_t bp = ballot(pass);
+        if (pass) pend2[npend2 + __builtin_popcountll(bp & below)] = ent;
+        npend2 += __builtin_popcountll(bp);
+        if (npend2 >= 64) {
+            __syncthreads();
+            rescore(pend2, 64);
+            const int rest = npend2 - 64;
+            const int2 t = (lane < rest) ? pend2[64 + lane] : make_int2(0, -1);
+            __syncthreads();
+            if (lane < rest) pend2[lane] = t;
+            npend2 = rest;
+        }
     };
 
     for (int base = 0; base < tot; base += 64) {
@@ -356,7 +484,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
         npend += __builtin_popcountll(bk);
         if (npend >= 64) {
             __syncthreads();
-            rescore(64);
+            if (CASC) cascade(64); else rescore(pend, 64);
             const int rest = npend - 64;
             const int2 t = (lane < rest) ? pend[64 + lane] : make_int2(0, -1);
             __syncthreads();
@@ -366,7 +494,11 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     }
     if (npend > 0) {
         __syncthreads();
-        rescore(npend);
+        if (CASC) cascade(npend); else rescore(pend, npend);
+    }
+    if (CASC && npend2 > 0) {
+        __syncthreads();
+        rescore(pend2, npend2);
     }
     if (lost || nk < K) {
         if (lane == 0) flag_user(a, u);
@@ -589,12 +721,23 @@ hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t 
     if (wave) {
         const uintptr_t base = (uintptr_t)a.I;
         const dim3 grid((unsigned)(p.n_ublk * 32)), blk(64);
-        if (p.f % 4 == 0 && base % 16 == 0)
-            certify_wave_kernel<4><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
-        else if (p.f % 2 == 0 && base % 8 == 0)
-            certify_wave_kernel<2><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
-        else
-            certify_wave_kernel<1><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        // bfloat16 cascade for E4M3 screens when the caller prepared its rows
+        const bool casc = p.prec == PREC_FP8 && a.qrow_b != nullptr;
+        if (casc) {
+            if (p.f % 4 == 0 && base % 16 == 0)
+                certify_wave_kernel<4, true><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+            else if (p.f % 2 == 0 && base % 8 == 0)
+                certify_wave_kernel<2, true><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+            else
+                certify_wave_kernel<1, true><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        } else {
+            if (p.f % 4 == 0 && base % 16 == 0)
+                certify_wave_kernel<4, false><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+            else if (p.f % 2 == 0 && base % 8 == 0)
+                certify_wave_kernel<2, false><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+            else
+                certify_wave_kernel<1, false><<<grid, blk, 0, s>>>(a, p.UB, p.n_ublk);
+        }
         return hipGetLastError();
     }
     // lanes per user G and LDS slots per lane EM (pairs whose key reaches

@@ -88,6 +88,12 @@ struct ScreenArgs {
     // per-item scalars by item index
     const float* Corig;       // ||i|| rounded up
     const float* Gorig;       // ||i - screen(i)|| + gamma ||screen(i)||, rounded up
+    // E4M3 certification cascade: a bfloat16 re-screen of the candidates
+    // before the float64 rescore (qrow_b null: no cascade)
+    const void* qrow_b;       // n_i x fpb bfloat16 copies by item index
+    const float* Gorig_b;     // ||i - bf16(i)|| + gamma_b ||bf16(i)||, rounded up
+    const unsigned int* maxb; // float bits of max ||i||, max ||bf16(i)||, max Gorig_b
+    int fpb;                  // bfloat16 row stride (multiple of 8, >= f)
     // per-call state
     int want_stats;           // accumulate the optional statistics (atomics)
     Ctrl* ctrl;
@@ -172,6 +178,11 @@ private:
     hipEvent_t start_ = nullptr, stop_ = nullptr;
     bool active_ = false;
 };
+
+// Whether E4M3 certification re-screens its candidates in bfloat16 before the
+// float64 rescore (environment MIPS_CERTIFY_CASCADE=1; off by default, as it
+// was measured slower on every workload here).
+bool cascade_enabled();
 
 // Copies the control block to the host (synchronising `s`) and fills the
 // public statistics struct.

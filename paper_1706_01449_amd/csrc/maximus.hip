@@ -525,6 +525,7 @@ struct mips_maximus_index {
     int* kexp = nullptr;
     float2* cblockmax[3] = {nullptr, nullptr, nullptr};
     unsigned int maxbits[3][3] = {};
+    Ctrl* prep_ctrl = nullptr;            // device copies of maxbits, one Ctrl per precision
     // walk tiles for 1, 2 and 4 user blocks per wave
     int4* tiles[3] = {nullptr, nullptr, nullptr};
     int64_t ntiles[3] = {0, 0, 0};
@@ -782,6 +783,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         Ctrl* tctrl = nullptr;
         float* Etmp = nullptr;
         TRY(dalloc(ix, &tctrl, 3), "alloc");
+        ix->prep_ctrl = tctrl;
         TRY(dalloc(ix, &Etmp, (size_t)n_i), "alloc");
         TRY(dalloc(ix, &ix->kexp, (size_t)n_i), "alloc");
         TRY(launch_zero(tctrl, 3 * sizeof(Ctrl), s), "zero");
@@ -928,6 +930,15 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
     a.kexp = ix->kexp;
     a.Corig = ix->Corig[precision];
     a.Gorig = ix->Gorig[precision];
+    if (precision == PREC_FP8 && ix->qrow[PREC_BF16] && cascade_enabled()) {
+        // bfloat16 rows of the index for the certification cascade
+        ScreenPlan pb;
+        make_screen_plan(1, ix->n_i, ix->f, 1, PREC_BF16, 0, &pb);
+        a.qrow_b = ix->qrow[PREC_BF16];
+        a.Gorig_b = ix->Gorig[PREC_BF16];
+        a.maxb = &ix->prep_ctrl[PREC_BF16].cmax_bits;
+        a.fpb = pb.f_pad;
+    }
     a.want_stats = want_stats;
     a.ctrl = ctrl;
     a.uflag = uflag;

@@ -189,24 +189,27 @@ def test_forced_candidate_overflow_stays_exact(prec, monkeypatch):
     assert_parity(idx, score, U, I, 10)
 
 
-@pytest.mark.parametrize("mode", ["wave", "group"])
+@pytest.mark.parametrize("mode", ["wave-cascade", "wave", "group"])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("shape", [(300, 2000, 50, 10), (200, 1500, 64, 32), (150, 1000, 33, 50),
                                    (97, 700, 100, 64), (64, 40, 7, 40)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_certification_kernels(mode, prec, shape, monkeypatch):
     """Both certification kernels (one wave per user with LDS-staged rows and
-    a rising threshold, or a group of lanes per user) give the oracle's
-    answer: f odd, even and a multiple of 4 (row loads of 1, 2 and 4 floats),
-    K past the fused sizes, duplicate rows that tie."""
+    a rising threshold, with or without the bfloat16 cascade of E4M3
+    candidates, or a group of lanes per user) give the oracle's answer: f
+    odd, even and a multiple of 4 (row loads of 1, 2 and 4 floats), K past
+    the fused sizes, duplicate rows that tie."""
     n_u, n_i, f, K = shape
     log(f"certify {mode} {shape} prec={prec}")
     U, I = mipsgen.generate("mf", 9, n_users=n_u, n_items=n_i, f=f)
     I[3] = I[n_i // 2]
     I[n_i - 1] = I[n_i // 2]
-    monkeypatch.setenv("MIPS_DEBUG_CERTIFY", mode)
+    monkeypatch.setenv("MIPS_DEBUG_CERTIFY", mode.split("-")[0])
+    monkeypatch.setenv("MIPS_CERTIFY_CASCADE", "1" if mode.endswith("cascade") else "0")
     idx, score, st = gpu_topk(U, I, K, prec, stats=True)
     monkeypatch.delenv("MIPS_DEBUG_CERTIFY")
+    monkeypatch.delenv("MIPS_CERTIFY_CASCADE")
     assert_parity(idx, score, U, I, K)
     assert st["rescored_pairs"] <= st["candidates_total"]
 

@@ -82,16 +82,19 @@ def test_query_small_all_users(prec, C, K):
         assert st["mean_items_visited"] < 0.5 * I.shape[0]
 
 
-@pytest.mark.parametrize("mode", ["wave", "group"])
-@pytest.mark.parametrize("prec,K", [("fp32", 32), ("bf16", 50), ("fp8", 10)])
+@pytest.mark.parametrize("mode", ["wave-cascade", "wave", "group"])
+@pytest.mark.parametrize("prec,K", [("fp32", 32), ("bf16", 50), ("fp8", 10), ("fp8", 40)])
 def test_query_certification_kernels(mode, prec, K, monkeypatch):
-    """The walk's candidates certified by either certification kernel."""
+    """The walk's candidates certified by either certification kernel, with
+    and without the bfloat16 cascade of E4M3 candidates."""
     log(f"maximus certify {mode} prec={prec} K={K}")
     U, I = mipsgen.generate("clustered", 5, n_users=3000, n_items=2500, f=50)
     ix = _build(U, I, 16)
-    monkeypatch.setenv("MIPS_DEBUG_CERTIFY", mode)
+    monkeypatch.setenv("MIPS_DEBUG_CERTIFY", mode.split("-")[0])
+    monkeypatch.setenv("MIPS_CERTIFY_CASCADE", "1" if mode.endswith("cascade") else "0")
     idx, score = _query(ix, K, prec)
     monkeypatch.delenv("MIPS_DEBUG_CERTIFY")
+    monkeypatch.delenv("MIPS_CERTIFY_CASCADE")
     assert_parity(idx, score, U, I, K)
 
 
