@@ -530,21 +530,42 @@ struct mips_maximus_index {
     int4* tiles[3] = {nullptr, nullptr, nullptr};
     int64_t ntiles[3] = {0, 0, 0};
     std::vector<void*> allocs;
+    char* arena = nullptr;                // free space of the current chunk
+    size_t arena_left = 0;
 };
 
 namespace {
 
 int ub_slot(int UB) { return UB == 1 ? 0 : (UB == 2 ? 1 : 2); }
 
+// Device memory of the index comes from a few chunks of kIndexChunk bytes
+// (one hipMalloc and one hipFree each), carved into 256-byte aligned pieces;
+// a piece of at least a chunk gets an allocation of its own.
+constexpr size_t kIndexChunk = (size_t)32 << 20;
+
 template <typename T>
 hipError_t dalloc(mips_maximus_index* ix, T** p, size_t count) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
-    if (e == hipSuccess) {
+    const size_t bytes = ((count * sizeof(T) > 0 ? count * sizeof(T) : 1) + 255) & ~(size_t)255;
+    if (bytes >= kIndexChunk) {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return e;
         ix->allocs.push_back(q);
         *p = (T*)q;
+        return hipSuccess;
     }
-    return e;
+    if (bytes > ix->arena_left) {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, kIndexChunk);
+        if (e != hipSuccess) return e;
+        ix->allocs.push_back(q);
+        ix->arena = (char*)q;
+        ix->arena_left = kIndexChunk;
+    }
+    *p = (T*)ix->arena;
+    ix->arena += bytes;
+    ix->arena_left -= bytes;
+    return hipSuccess;
 }
 
 void free_index(mips_maximus_index* ix) {
