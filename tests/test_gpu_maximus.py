@@ -98,6 +98,21 @@ def test_query_certification_kernels(mode, prec, K, monkeypatch):
     assert_parity(idx, score, U, I, K)
 
 
+@pytest.mark.parametrize("cap", [12, 40])
+def test_e4m3_walk_forced_overflow(cap, monkeypatch):
+    """A test-only cap of a few candidate slots per lane overflows the E4M3
+    walk's lists for many users, which then take the exact float64 path; the
+    answer must not change."""
+    log(f"maximus e4m3 forced overflow cap={cap}")
+    U, I = mipsgen.generate("clustered", 6, n_users=3000, n_items=2500, f=50)
+    ix = _build(U, I, 16)
+    monkeypatch.setenv("MIPS_DEBUG_CAND_CAP", str(cap))
+    idx, score, st = _query(ix, 10, "fp8", stats=True)
+    monkeypatch.delenv("MIPS_DEBUG_CAND_CAP")
+    log(f"  overflow users {st['overflow_users']} of {U.shape[0]}")
+    assert_parity(idx, score, U, I, 10)
+
+
 def test_singleton_clusters_and_degenerate_rows():
     U, I = mipsgen.generate("mf", 3, n_users=300, n_items=900, f=20)
     U[5] = 0.0
