@@ -238,8 +238,11 @@ int mips_optimus_topk(const float* U, int64_t n_u, const float* I, int64_t n_i, 
  *   dU[u]  = sum_k G[u,k] I[idx[u,k]]                      (gather)
  *   dI[i]  = sum over (u,k) with idx[u,k] = i of G[u,k] U[u]  (scatter-add)
  * dU (n_u x f) and dI (n_i x f) are overwritten.  dU is summed in k order
- * and is deterministic; dI is accumulated with float32 atomics, so its last
- * bits may vary run to run.  idx entries outside [0, n_i) are skipped.
+ * and is deterministic.  For dI the pairs are grouped by item and summed in
+ * runs, each run added with float32 atomics, so its last bits may vary run
+ * to run.  idx entries outside [0, n_i) are skipped.  The grouping takes
+ * stream-ordered scratch (hipMallocAsync / hipFreeAsync on `stream`) of
+ * about 12 n_i + 4 n_u K bytes.
  * Limits: 1 <= n_u, n_i < 2^31; 1 <= f <= 4096; K >= 1.
  * ------------------------------------------------------------------------- */
 int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
