@@ -117,3 +117,31 @@ def test_out_of_range_indices_are_skipped():
     rU, rI = B.scatter_gather_grads(U, I, idx2, G2)
     _close(dU.cpu().numpy(), rU)
     _close(dI.cpu().numpy(), rI)
+
+
+def test_grouping_with_colliding_items_and_popular_items():
+    """The dI grouping counts pairs per item in per-workgroup hash tables: items
+    whose hashes collide (probe sequences past the table's limit take the
+    global path) and a few items shared by almost every user (long runs that
+    span workgroups) must still give the plain gather/scatter result."""
+    import paper_1706_01449_amd as mips
+    n_i, f, n_u, K = 1 << 20, 4, 600, 24
+    # items whose 13-bit multiplicative hash is equal: they probe the same slots
+    h = ((np.arange(n_i, dtype=np.uint64) * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)) >> np.uint64(19)
+    same = np.nonzero(h == h[12345])[0][:100].astype(np.int32)
+    assert same.size == 100
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((n_u, f)).astype(np.float32)
+    I = rng.standard_normal((n_i, f)).astype(np.float32)
+    idx = np.empty((n_u, K), dtype=np.int32)
+    for u in range(n_u):
+        idx[u, :16] = rng.choice(same, 16, replace=False)   # colliding items
+        idx[u, 16:20] = [7, 8, 9, 10]                        # items of every user
+        idx[u, 20:] = rng.integers(0, n_i, 4)
+    G = rng.standard_normal((n_u, K)).astype(np.float32)
+    Ut, It = to_dev(U, I)
+    dU, dI = mips.topk_backward(Ut, It, torch.from_numpy(idx).to(DEV), torch.from_numpy(G).to(DEV))
+    torch.cuda.synchronize()
+    rU, rI = B.scatter_gather_grads(U, I, idx, G)
+    _close(dU.cpu().numpy(), rU)
+    _close(dI.cpu().numpy(), rI)
