@@ -608,10 +608,13 @@ __global__ void __launch_bounds__(256) fallback_keys_kernel(const FallbackArgs a
     }
 }
 
+// KMAX: the largest K the kernel serves (its LDS slots for the selected
+// pairs); the small instance leaves room for several workgroups per CU.
+template <int KMAX>
 __global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
     __shared__ unsigned int hist[256];
-    __shared__ double skey[kFallbackMaxK];
-    __shared__ int sidx[kFallbackMaxK];
+    __shared__ double skey[KMAX];
+    __shared__ int sidx[KMAX];
     __shared__ float su[256];
     __shared__ float srow[kFbRows][kFbCols + 1];
     __shared__ unsigned long long s_prefix;
@@ -672,7 +675,7 @@ __global__ void __launch_bounds__(256) fallback_kernel(const FallbackArgs a) {
             const unsigned int chunk_eq = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
             if (gt || (eq && rank < take_eq)) {
                 const unsigned int slot = atomicAdd(&s_sel, 1u);
-                if (slot < (unsigned)kFallbackMaxK) { skey[slot] = k; sidx[slot] = (int)i; }
+                if (slot < (unsigned)KMAX) { skey[slot] = k; sidx[slot] = (int)i; }
             }
             eq_before += chunk_eq;
             __syncthreads();
@@ -771,7 +774,10 @@ hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a_in, hipStr
     fallback_keys_kernel<<<dim3(xb, 16), dim3(256), 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    fallback_kernel<<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
+    if (a.K <= 64)
+        fallback_kernel<64><<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
+    else
+        fallback_kernel<kFallbackMaxK><<<dim3((unsigned)p.fb_grid), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
 
