@@ -239,6 +239,14 @@ __device__ __forceinline__ float list_tau(const float (&l)[KM], int hidx, bool k
     return vmax(vmax(t, tp), vmin(th, thp));
 }
 
+// The walk tests each hit against the pair's own bound (the item norms of
+// its tile, gathered with the operands) where the extra registers keep two
+// waves per SIMD: lists of up to 16 entries, at most 64 bfloat16 or 32
+// float32 factors.
+__host__ __device__ constexpr bool pair_bound_walk(bool walk, int prec, int km, int nch) {
+    return walk && km <= 16 && (prec != PREC_BF16 || nch <= 4) && (prec != PREC_FP32 || nch <= 16);
+}
+
 // Warm-up sets of per-slot maxima (16 slots per set) used to seed tau.
 __host__ __device__ constexpr int warm_sets(int km) {
     return km <= 16 ? 2 : (km <= 32 ? 3 : 4);
@@ -395,7 +403,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // This lane's A-operand chunks of tile b (row n), the row's item index
     // (-1 past the end) and, for E4M3, the row's E8M0 scale byte.
-    auto load_tile = [&](int b, Op (&ai)[NCH], int& item, int& iscale, float2& bm)
+    auto load_tile = [&](int b, Op (&ai)[NCH], int& item, int& iscale, float2& bm, float2& cg)
         __attribute__((always_inline)) {
         const int64_t p = (int64_t)b * kTile + n;
         bm = bmax[b];
@@ -408,6 +416,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         } else {
             item = clist[p];                        // -1 past the last item
             const int64_t row = item >= 0 ? item : 0;
+            if constexpr (pair_bound_walk(WALK, PREC, KM, NCH))
+                cg = make_float2(a.Corig[row], a.Gorig[row]);   // for the per-pair bound
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 ai[c] = P::load_row(a.qrow, row, a.f_pad, h * half + c * E);
@@ -458,7 +468,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     Op ai[NCH];
                     int it = -1, sc = 127;
                     float2 bmw;
-                    load_tile(b, ai, it, sc, bmw);
+                    float2 cgw;
+                    load_tile(b, ai, it, sc, bmw, cgw);
                     floatx16_t acc[UB];
                     score_tile(b, ai, sc, acc);
 #pragma unroll
@@ -483,7 +494,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 
     // Streaming top-K over tile b; returns false once every user of a walk
     // wave has stopped.
-    auto epi_tile = [&](int b, floatx16_t (&acc)[UB], int item, float2 bm)
+    auto epi_tile = [&](int b, floatx16_t (&acc)[UB], int item, float2 bm, float2 cg)
         __attribute__((always_inline)) -> bool {
 #pragma unroll
         for (int ub = 0; ub < UB; ++ub) {
@@ -505,13 +516,25 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     for (int q = 0; q < 4; ++q) {
                         const int r = 4 * g + q;
                         const float v = acc[ub][r];
-                        const bool hit = (v >= thr) && (v > ninf);
+                        bool hit = (v >= thr) && (v > ninf);
                         if (ballot(hit)) {
                             // item index of output row 8g + 4h + q, held by lane (row)
                             const int row = 8 * g + 4 * h + q;
                             const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
+                            float lb = v - ee;
+                            if constexpr (pair_bound_walk(WALK, PREC, KM, NCH)) {
+                                // walk tiles mix item norms, so the tile's
+                                // bound is loose: test the pair's own bound
+                                const float ci = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.x)));
+                                const float gi = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.y)));
+                                const float ei = fmaf(Au[ub], ci, fmaf(Bu[ub], gi, slk[ub]));
+                                hit = hit && (v + ei >= tauf[ub]);
+                                lb = v - ei;
+                            }
                             if (hit) {
-                                list_insert(lst[ub], v - ee);
+                                list_insert(lst[ub], lb);
                                 if (cnt[ub] < a.cap)
                                     cptr[ub][cnt[ub]] = make_int2(__float_as_int(v), orig);
                                 cnt[ub] += 1;
@@ -564,22 +587,22 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         const int last = n_blk - 1;
         Op oA[NCH], oB[NCH];
         int itA = -1, itB = -1, scA = 127, scB = 127;
-        float2 bmA, bmB;
+        float2 bmA, bmB, cgA = make_float2(0.0f, 0.0f), cgB = make_float2(0.0f, 0.0f);
         floatx16_t acc[UB];
-        load_tile(0, oA, itA, scA, bmA);
-        load_tile(n_blk > 1 ? 1 : 0, oB, itB, scB, bmB);
+        load_tile(0, oA, itA, scA, bmA, cgA);
+        load_tile(n_blk > 1 ? 1 : 0, oB, itB, scB, bmB, cgB);
         for (int b = 0; b < n_blk; b += 2) {
             score_tile(b, oA, scA, acc);
             const int eA = itA;
-            const float2 mA = bmA;
-            load_tile(b + 2 < last ? b + 2 : last, oA, itA, scA, bmA);
-            if (!epi_tile(b, acc, eA, mA)) { b_done = b + 1; break; }
+            const float2 mA = bmA, gA = cgA;
+            load_tile(b + 2 < last ? b + 2 : last, oA, itA, scA, bmA, cgA);
+            if (!epi_tile(b, acc, eA, mA, gA)) { b_done = b + 1; break; }
             if (b + 1 >= n_blk) break;
             score_tile(b + 1, oB, scB, acc);
             const int eB = itB;
-            const float2 mB = bmB;
-            load_tile(b + 3 < last ? b + 3 : last, oB, itB, scB, bmB);
-            if (!epi_tile(b + 1, acc, eB, mB)) { b_done = b + 2; break; }
+            const float2 mB = bmB, gB = cgB;
+            load_tile(b + 3 < last ? b + 3 : last, oB, itB, scB, bmB, cgB);
+            if (!epi_tile(b + 1, acc, eB, mB, gB)) { b_done = b + 2; break; }
         }
     }
 
