@@ -67,7 +67,10 @@ typedef enum {
 typedef enum {
     MIPS_PREC_FP32 = 0,         /* float32 matrix-core screen                          */
     MIPS_PREC_BF16 = 1,         /* bfloat16 (round-to-nearest-even) screen             */
-    MIPS_PREC_FP8_E4M3 = 2      /* OCP E4M3 screen with per-row power-of-two scales    */
+    MIPS_PREC_FP8_E4M3 = 2,     /* OCP E4M3 screen with per-row power-of-two scales    */
+    MIPS_PREC_FP8_E4M3_BF16 = 3 /* the E4M3 screen, its candidates re-screened in       *
+                                 * bfloat16 (with the bfloat16 bound) before the        *
+                                 * float64 rescore: fewer pairs rescored, more passes   */
 } mips_precision;
 
 /* Host-side counters of one call; filled only when a non-NULL pointer is passed. */
@@ -254,6 +257,20 @@ int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i,
  * ------------------------------------------------------------------------- */
 const char* mips_status_string(int status);
 const char* mips_last_error_message(void);
+
+/* Testing only.  Process-wide knobs that force rare paths so tests can reach
+ * them on small inputs; 0 (the initial value) means normal operation.  They
+ * change speed, never the result:
+ *   MIPS_DEBUG_CAND_CAP        candidate slots per lane of the screen (>= 1);
+ *                              a small cap overflows the lists and sends users
+ *                              to the exact float64 fallback
+ *   MIPS_DEBUG_CERTIFY_KERNEL  1 = certify with one wave per user, 2 = with a
+ *                              group of lanes per user (where the screen does
+ *                              not certify in its own tail)
+ * Returns MIPS_ERR_ARG for an unknown knob or value.  Not for concurrent use
+ * with calls that read the knobs. */
+typedef enum { MIPS_DEBUG_CAND_CAP = 0, MIPS_DEBUG_CERTIFY_KERNEL = 1 } mips_debug_knob;
+int mips_debug_set(int32_t knob, int32_t value);
 
 /* Kernel timing.  While enabled, every kernel phase launched by this library
  * is bracketed by HIP events recorded on the caller's stream (no host

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -75,10 +76,9 @@ PhaseTimer::~PhaseTimer() {
 // ---------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool cascade_enabled() {
-    const char* env = std::getenv("MIPS_CERTIFY_CASCADE");
-    return env && std::strcmp(env, "1") == 0;
-}
+static std::atomic<int> g_dbg_cand_cap{0}, g_dbg_certify{0};
+int debug_cand_cap() { return g_dbg_cand_cap.load(std::memory_order_relaxed); }
+int debug_certify_kernel() { return g_dbg_certify.load(std::memory_order_relaxed); }
 
 bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t, ScreenPlan* out) {
     ScreenPlan p;
@@ -115,12 +115,8 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
         p.cap = std::max(512, 8 * p.KM + 64);
     else
         p.cap = std::max(64, 2 * p.KM + 32);
-    // Test-only override of the candidate slots per lane (forces the overflow
-    // fallback when small); read from the environment at every call.
-    if (const char* env = std::getenv("MIPS_DEBUG_CAND_CAP")) {
-        int v = std::atoi(env);
-        if (v >= 1) p.cap = v;
-    }
+    // Test knob: fewer candidate slots per lane (forces the overflow fallback).
+    if (const int v = debug_cand_cap(); v >= 1) p.cap = v;
     p.kc = p.cap;
     p.n_blk = (n_i + 31) / 32;
     p.n_i_pad = p.n_blk * 32;
@@ -190,7 +186,7 @@ static int check_common(int64_t n_u, int64_t n_i, int f, int K, int prec) {
     if (n_u >= ((int64_t)1 << 31)) return fail(MIPS_ERR_ARG, "n_u must be < 2^31");
     if (f < 1 || f > 256) return fail(MIPS_ERR_ARG, "f must be in [1, 256] (got %d)", f);
     if (K < 1 || (int64_t)K > n_i) return fail(MIPS_ERR_ARG, "K must be in [1, n_i] (got %d)", K);
-    if (prec < PREC_FP32 || prec > PREC_FP8) return fail(MIPS_ERR_ARG, "unknown precision %d", prec);
+    if (!valid_prec(prec)) return fail(MIPS_ERR_ARG, "unknown precision %d", prec);
     if (K > kFallbackMaxK)
         return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported (got %d)", kFallbackMaxK, K);
     return MIPS_OK;
@@ -291,8 +287,20 @@ size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t
                                     int32_t precision) {
     if (check_common(n_u, n_i, f, K, precision) != MIPS_OK) return 0;
     ScreenPlan p;
-    make_screen_plan(n_u, n_i, f, K, precision, 0, &p);
+    make_screen_plan(n_u, n_i, f, K, screen_prec(precision), 0, &p);
     return bmm_layout(p).total;
+}
+
+int mips_debug_set(int32_t knob, int32_t value) {
+    if (value < 0) return fail(MIPS_ERR_ARG, "debug knob values are >= 0 (got %d)", value);
+    switch (knob) {
+        case MIPS_DEBUG_CAND_CAP: g_dbg_cand_cap.store(value); return MIPS_OK;
+        case MIPS_DEBUG_CERTIFY_KERNEL:
+            if (value > 2) return fail(MIPS_ERR_ARG, "certification kernel must be 0, 1 or 2");
+            g_dbg_certify.store(value);
+            return MIPS_OK;
+        default: return fail(MIPS_ERR_ARG, "unknown debug knob %d", knob);
+    }
 }
 
 }  // extern "C"
@@ -304,6 +312,8 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
     int rc = check_common(n_u, n_i, f, K, precision);
     if (rc != MIPS_OK) return rc;
     if (!U || !I || !out_idx || !out_score) return fail(MIPS_ERR_ARG, "null array pointer");
+    const bool casc = cascade_of(precision);
+    precision = screen_prec(precision);
     ScreenPlan p;
     make_screen_plan(n_u, n_i, f, K, precision, 0, &p);
     const BmmLayout L = bmm_layout(p);
@@ -341,7 +351,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
             ia.ctrl = ctrl;
             if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
                 return hip_fail(e, "item preparation");
-            if (precision == PREC_FP8 && cascade_enabled()) {
+            if (casc) {
                 // bfloat16 rows and residual norms for the certification cascade
                 ItemPrepArgs ib{};
                 ib.I = I;
@@ -401,7 +411,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
         a.kexp = (const int*)(ws + L.kexp);
         a.Corig = (const float*)(ws + L.Corig);
         a.Gorig = (const float*)(ws + L.Gorig);
-        if (precision == PREC_FP8 && cascade_enabled()) {
+        if (casc) {
             a.qrow_b = ws + L.qrowb;
             a.Gorig_b = (const float*)(ws + L.Gorigb);
             a.maxb = &((const Ctrl*)(ws + L.ctrlb))->cmax_bits;

@@ -714,13 +714,11 @@ hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s
 hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     if (fused_certify(p.prec, p.KM, p.UB)) return hipSuccess;   // done by the screen kernel
     // one wave per user for long candidate lists (E4M3, or K > 16), a group
-    // of lanes per user for short ones (MIPS_DEBUG_CERTIFY = "wave" or
-    // "group" forces either kernel, for tests)
+    // of lanes per user for short ones (the certification test knob forces
+    // either kernel)
     bool wave = p.prec == PREC_FP8 || p.K > 16;
-    if (const char* env = std::getenv("MIPS_DEBUG_CERTIFY")) {
-        if (std::strcmp(env, "wave") == 0) wave = true;
-        if (std::strcmp(env, "group") == 0) wave = false;
-    }
+    if (debug_certify_kernel() == 1) wave = true;
+    if (debug_certify_kernel() == 2) wave = false;
     if (wave) {
         const uintptr_t base = (uintptr_t)a.I;
         const dim3 grid((unsigned)(p.n_ublk * 32)), blk(64);

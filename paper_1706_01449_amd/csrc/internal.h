@@ -10,8 +10,15 @@
 
 namespace mips {
 
-// Precision codes (same values as the public mips_precision enum).
-enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
+// Precision codes (same values as the public mips_precision enum).  The
+// public code PREC_FP8_CASCADE selects the E4M3 screen whose candidates are
+// re-screened in bfloat16 before the float64 rescore; every kernel sees the
+// screen precision PREC_FP8 and a separate cascade flag.
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2, PREC_FP8_CASCADE = 3 };
+
+inline int screen_prec(int p) { return p == PREC_FP8_CASCADE ? PREC_FP8 : p; }
+inline bool cascade_of(int p) { return p == PREC_FP8_CASCADE; }
+inline bool valid_prec(int p) { return p >= PREC_FP32 && p <= PREC_FP8_CASCADE; }
 
 // User blocks of 32 per screen wave.  Each user block holds its operand
 // registers, two accumulator sets (software pipeline) and a KM-entry K-list,
@@ -179,10 +186,11 @@ private:
     bool active_ = false;
 };
 
-// Whether E4M3 certification re-screens its candidates in bfloat16 before the
-// float64 rescore (environment MIPS_CERTIFY_CASCADE=1; off by default, as it
-// was measured slower on every workload here).
-bool cascade_enabled();
+// Test knobs set through mips_debug_set (0 = normal operation): a smaller
+// number of candidate slots per lane, and the certification kernel to use
+// (1 one wave per user, 2 a group of lanes per user).
+int debug_cand_cap();
+int debug_certify_kernel();
 
 // Copies the control block to the host (synchronising `s`) and fills the
 // public statistics struct.

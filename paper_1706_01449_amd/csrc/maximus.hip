@@ -892,10 +892,10 @@ void mips_maximus_free(mips_maximus_index* index) { free_index(index); }
 static int64_t walk_cap_check(const ScreenPlan& p) { return p.cap; }
 
 size_t mips_maximus_query_workspace_size(const mips_maximus_index* ix, int32_t K, int32_t precision) {
-    if (!ix || K < 1 || (int64_t)K > ix->n_i || K > kFallbackMaxK || precision < 0 || precision > 2)
+    if (!ix || K < 1 || (int64_t)K > ix->n_i || K > kFallbackMaxK || !valid_prec(precision))
         return 0;
     ScreenPlan p;
-    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, precision, 0, &p);
+    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
     const int64_t nw = p.fast ? ix->ntiles[ub_slot(p.UB)] : 0;
     const int64_t n_ublk = nw * p.UB;
     size_t o = 0;
@@ -917,7 +917,7 @@ namespace {
 // Walk (screen over the cluster lists), certification and the exact
 // fallback for the users named by `tiles` / `sorted_users` (rows of U).
 int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int precision,
-                          const float* U, int64_t n_u, const int4* tiles, const int* sorted_users,
+                          bool casc, const float* U, int64_t n_u, const int4* tiles, const int* sorted_users,
                           Ctrl* ctrl, int* uflag, int* flist, float4* uscal, int* cnt, int2* cand,
                           double* fbkeys, int32_t* out_idx, double* out_score, bool want_stats,
                           hipStream_t s) {
@@ -951,7 +951,7 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
     a.kexp = ix->kexp;
     a.Corig = ix->Corig[precision];
     a.Gorig = ix->Gorig[precision];
-    if (precision == PREC_FP8 && ix->qrow[PREC_BF16] && cascade_enabled()) {
+    if (casc && ix->qrow[PREC_BF16]) {
         // bfloat16 rows of the index for the certification cascade
         ScreenPlan pb;
         make_screen_plan(1, ix->n_i, ix->f, 1, PREC_BF16, 0, &pb);
@@ -1005,7 +1005,7 @@ int check_query_args(const mips_maximus_index* ix, int32_t K, int32_t precision,
     if (!out_idx || !out_score) return fail(MIPS_ERR_ARG, "null output pointer");
     if (K < 1 || (int64_t)K > ix->n_i) return fail(MIPS_ERR_ARG, "K must be in [1, n_i] (got %d)", K);
     if (K > kFallbackMaxK) return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported", kFallbackMaxK);
-    if (precision < 0 || precision > 2) return fail(MIPS_ERR_ARG, "unknown precision %d", precision);
+    if (!valid_prec(precision)) return fail(MIPS_ERR_ARG, "unknown precision %d", precision);
     return MIPS_OK;
 }
 
@@ -1056,7 +1056,7 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
     if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     ScreenPlan p;
-    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, precision, 0, &p);
+    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
     const int slot = ub_slot(p.UB);
     p.n_waves = p.fast ? ix->ntiles[slot] : 0;
     p.n_ublk = p.n_waves * p.UB;
@@ -1074,7 +1074,7 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
     double* fbkeys = (double*)take((size_t)p.fb_grid * ix->n_i * 8);
     hipError_t e;
     if ((e = launch_zero(ws, zero_bytes, s)) != hipSuccess) return hip_fail(e, "zero");
-    rc = walk_certify_fallback(ix, p, precision, ix->U, ix->n_u, ix->tiles[slot], ix->sorted_users,
+    rc = walk_certify_fallback(ix, p, screen_prec(precision), cascade_of(precision), ix->U, ix->n_u, ix->tiles[slot], ix->sorted_users,
                                ctrl, uflag, flist, uscal, cnt, cand, fbkeys, out_idx, out_score,
                                stats != nullptr, s);
     if (rc != MIPS_OK) return rc;
@@ -1092,10 +1092,10 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
 size_t mips_maximus_query_users_workspace_size(const mips_maximus_index* ix, int64_t n_q,
                                                int32_t K, int32_t precision) {
     if (!ix || n_q < 1 || n_q >= ((int64_t)1 << 31) || K < 1 || (int64_t)K > ix->n_i ||
-        K > kFallbackMaxK || precision < 0 || precision > 2)
+        K > kFallbackMaxK || !valid_prec(precision))
         return 0;
     ScreenPlan p;
-    make_screen_plan(n_q, ix->n_i, ix->f, K, precision, 0, &p);
+    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
     return query_layout(ix, p, n_q).total;
 }
 
@@ -1113,7 +1113,7 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     ScreenPlan p;
-    make_screen_plan(n_q, ix->n_i, ix->f, K, precision, 0, &p);
+    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
     const QueryLayout L = query_layout(ix, p, n_q);
     p.n_waves = L.max_tiles;
     p.n_ublk = p.n_waves * p.UB;
@@ -1143,7 +1143,7 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
         qscatter_kernel<<<grid_of(n_q), 256, 0, s>>>(n_q, qassign, uflag, ccount + kBuckets, sorted);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "user grouping");
     }
-    rc = walk_certify_fallback(ix, p, precision, Uq, n_q, tiles, sorted, ctrl, uflag, flist, uscal,
+    rc = walk_certify_fallback(ix, p, screen_prec(precision), cascade_of(precision), Uq, n_q, tiles, sorted, ctrl, uflag, flist, uscal,
                                (int*)(ws + L.cnt), (int2*)(ws + L.cand), (double*)(ws + L.fbkeys),
                                out_idx, out_score, stats != nullptr, s);
     if (rc != MIPS_OK) return rc;

@@ -105,10 +105,13 @@ extern "C" int mips_optimus_topk(const float* U, int64_t n_u, const float* I, in
     if (n_u < 1 || n_u >= ((int64_t)1 << 31)) return fail(MIPS_ERR_ARG, "n_u must be in [1, 2^31)");
     if ((int64_t)n_clusters > n_u || n_clusters < 1 || n_clusters > 4096)
         return fail(MIPS_ERR_ARG, "n_clusters must be in [1, min(n_u, 4096)] (got %d)", n_clusters);
+    if (kmeans_iters < 0 || kmeans_iters > 100)
+        return fail(MIPS_ERR_ARG, "kmeans_iters must be in [0, 100] (got %d)", kmeans_iters);
     // argument checks of the two methods, before anything is enqueued
+    if (K > kFallbackMaxK && (int64_t)K <= n_i)
+        return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported", kFallbackMaxK);
     if (mips_bmm_topk_workspace_size(n_u, n_i, f, K, precision) == 0)
-        return fail(MIPS_ERR_ARG, "invalid sizes for the brute force");
-    if (K > kFallbackMaxK) return fail(MIPS_ERR_UNSUPPORTED, "K > %d is not supported", kFallbackMaxK);
+        return fail(MIPS_ERR_ARG, "invalid sizes or precision for the brute force");
     hipStream_t s = (hipStream_t)stream;
     mips_optimus_report rep{};
 

@@ -14,7 +14,8 @@ _LIB_PATH = os.path.join(_HERE, "_lib", "libmips.so")
 _HEADER = os.path.join(os.path.dirname(_HERE), "include", "mips.h")
 _lib = None
 
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2, "fp8_bf16": 3}
+DEBUG_KNOBS = {"cand_cap": 0, "certify_kernel": 1}
 PROFILE_PHASES = ["item_prep", "screen", "certify", "fallback", "build", "walk", "backward"]
 
 
@@ -119,6 +120,8 @@ def lib():
     L.mips_status_string.argtypes = [ctypes.c_int]
     L.mips_last_error_message.restype = ctypes.c_char_p
     L.mips_last_error_message.argtypes = []
+    L.mips_debug_set.restype = ctypes.c_int
+    L.mips_debug_set.argtypes = [c_i32, c_i32]
     L.mips_profile_enable.restype = ctypes.c_int
     L.mips_profile_enable.argtypes = [ctypes.c_int]
     L.mips_profile_read.restype = ctypes.c_int
@@ -339,6 +342,27 @@ def topk_backward(U: torch.Tensor, I: torch.Tensor, idx: torch.Tensor, grad_scor
     _check(lib().mips_topk_backward(U.data_ptr(), I.data_ptr(), n_u, n_i, f, K, idx.data_ptr(),
                                     g.data_ptr(), dU.data_ptr(), dI.data_ptr(), _stream(U.device)))
     return dU, dI
+
+
+def debug_set(knob: str, value: int):
+    """Set a test knob of the library (see mips_debug_set); 0 restores the
+    normal behaviour."""
+    _check(lib().mips_debug_set(DEBUG_KNOBS[knob], int(value)))
+
+
+class debug_knob:
+    """Context manager: a test knob set for the duration of a block."""
+
+    def __init__(self, knob: str, value: int):
+        self.knob, self.value = knob, value
+
+    def __enter__(self):
+        debug_set(self.knob, self.value)
+        return self
+
+    def __exit__(self, *exc):
+        debug_set(self.knob, 0)
+        return False
 
 
 def profile_enable(on: bool = True):

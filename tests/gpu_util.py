@@ -2,12 +2,17 @@
 compare with the CPU oracle element by element."""
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
 import torch
 
 from oracle import topk as oracle_topk
+
+MANIFESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "manifests")
 
 DEV = "cuda:0"
 
@@ -57,3 +62,44 @@ def assert_properties_all_users(idx, score, U, I, K):
         d = score[:, :-1] - score[:, 1:]
         ok = (d > 0) | ((d == 0) & (idx[:, :-1] < idx[:, 1:]))
         assert np.all(ok), "a row is not ordered by (key desc, index asc)"
+
+
+def _sha(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def load_manifest(workload: str, seed: int, K: int) -> dict:
+    path = os.path.join(MANIFESTS, f"{workload}_seed{seed}_K{K}.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def assert_manifest(idx, score, U, I, workload: str, seed: int, K: int, what: str = ""):
+    """Every user's answer equals the oracle's, bit for bit: the SHA-256 of
+    the GPU's idx (int32) and score (float64) bytes must equal the hashes the
+    oracle's full run wrote (tests/golden/make_manifests.py).  The inputs'
+    own hashes are checked first, so a changed generator is reported as such.
+    On a mismatch the differing blocks of users are named and a few users of
+    the first such block are compared element by element with the oracle."""
+    m = load_manifest(workload, seed, K)
+    assert _sha(U) == m["U_sha256"] and _sha(I) == m["I_sha256"], \
+        f"{workload} seed {seed}: input bytes differ from the ones the manifest was written for"
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    score = np.ascontiguousarray(score, dtype=np.float64)
+    assert idx.shape == (m["n_users"], K) and score.shape == (m["n_users"], K)
+    if _sha(idx) == m["idx_sha256"] and _sha(score) == m["key_sha256"]:
+        return
+    B = m["block_users"]
+    bad = [b for b in range(len(m["idx_block_sha256"]))
+           if _sha(idx[b * B:(b + 1) * B]) != m["idx_block_sha256"][b]
+           or _sha(score[b * B:(b + 1) * B]) != m["key_block_sha256"][b]]
+    msg = f"{what}: {len(bad)} of {len(m['idx_block_sha256'])} blocks of {B} users differ from the oracle"
+    if bad:
+        users = np.arange(bad[0] * B, min((bad[0] + 1) * B, m["n_users"]))[:256]
+        ri, rk = oracle_topk.topk(U[users], I, K)
+        diff = np.nonzero((idx[users] != ri).any(axis=1) | (score[users] != rk).any(axis=1))[0]
+        if diff.size:
+            u = users[diff[0]]
+            msg += (f"; user {u}: gpu {idx[u][:12]} {score[u][:4]} "
+                    f"oracle {ri[diff[0]][:12]} {rk[diff[0]][:4]}")
+    raise AssertionError(msg)

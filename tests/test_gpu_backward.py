@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import mipsgen
-from gpu_util import DEV, assert_properties_all_users, log, to_dev
+from gpu_util import DEV, assert_manifest, log, to_dev
 from oracle import backward as B
 from oracle import topk as oracle_topk
 
@@ -38,10 +38,7 @@ def test_full_size_grad_workload_direct():
     dU, dI = mips.topk_backward(Ut, It, idx, torch.from_numpy(G).to(DEV))
     torch.cuda.synchronize()
     idx_h = idx.cpu().numpy()
-    users = mipsgen.sample_users(U.shape[0], 2000, seed=5)
-    ri, _ = oracle_topk.topk(U[users], I, 32)
-    np.testing.assert_array_equal(idx_h[users], ri)
-    assert_properties_all_users(idx_h, score.cpu().numpy(), U, I, 32)
+    assert_manifest(idx_h, score.cpu().numpy(), U, I, "grad", 0, 32, what="grad forward")
     rU, rI = B.scatter_gather_grads(U, I, idx_h, G)
     _close(dU.cpu().numpy(), rU)
     _close(dI.cpu().numpy(), rI)
