@@ -206,18 +206,15 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
     pf = {}
     users = mipsgen.sample_users(U.shape[0], 100, seed=1)
     ri, rk = oracle_topk.topk(U[users], I, 10)
-    # "fp8_cascade": the E4M3 screen with the bfloat16 re-screen of its
-    # candidates before the float64 rescore (opt-in, MIPS_CERTIFY_CASCADE=1)
-    for name in ("bf16", "fp8", "fp8_cascade", "fp32"):
-        prec = name.split("_")[0]
-        if name == "fp8_cascade":
-            os.environ["MIPS_CERTIFY_CASCADE"] = "1"
+    # "fp8_bf16": the E4M3 screen with the bfloat16 re-screen of its
+    # candidates before the float64 rescore
+    for name in ("bf16", "fp8", "fp8_bf16", "fp32"):
+        prec = name
         ws = torch.empty(mips.lib().mips_bmm_topk_workspace_size(U.shape[0], I.shape[0], 100, 10,
                                                                   mips.PRECISIONS[prec]),
                          dtype=torch.uint8, device=dev)
         t = timed(torch, lambda: mips.bmm_topk(Ut, It, 10, prec, workspace=ws), 3)
         idx, score, st = mips.bmm_topk(Ut, It, 10, prec, stats=True, workspace=ws)
-        os.environ.pop("MIPS_CERTIFY_CASCADE", None)
         gi = idx.cpu().numpy()[users]
         gs = score.cpu().numpy()[users]
         pf[name] = {"ms": t, "users_per_s": U.shape[0] / (t * 1e-3),

@@ -7,6 +7,6 @@ the compiled library is missing the calls raise.
 """
 from .mips import (  # noqa: F401
     MipsError, PRECISIONS, bmm_topk, norm_pruned_topk, maximus_build, MaximusIndex, optimus_topk, topk_backward,
-    lib, lib_path, profile_enable, profile_read, PROFILE_PHASES, header_symbols,
+    lib, lib_path, profile_enable, profile_read, PROFILE_PHASES, header_symbols, debug_set, debug_knob,
 )
 from .autograd import TopKScores, topk_scores  # noqa: F401
