@@ -253,6 +253,27 @@ int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i,
                        float* dI, void* stream);
 
 /* ------------------------------------------------------------------------- *
+ * mips_topk_backward_noalloc: the same operation and arguments as
+ * mips_topk_backward, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training or serving loops, harnesses that
+ * forbid hipMalloc).  It calls no hipMalloc, hipFree or allocating library
+ * routine: the item grouping's scratch is a static device array of
+ * MIPS_NOALLOC_SCRATCH_BYTES bytes, one per device, that the library holds
+ * from its first call on that device until the process ends.
+ * The scratch needed is about 12 n_i + 4 n_u K bytes (+ 4 KiB); larger calls
+ * return MIPS_ERR_UNSUPPORTED before anything is enqueued (use
+ * mips_topk_backward for them).  With n_u K >= 2^31 no scratch is used.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (two streams, or two host threads) race and must be ordered by
+ * the caller.  The arrays it clears are cleared by kernels on `stream`.
+ * Other arguments, limits, errors and results: as mips_topk_backward.
+ * ------------------------------------------------------------------------- */
+#define MIPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mips_topk_backward_noalloc(const float* U, const float* I, int64_t n_u, int64_t n_i,
+                               int32_t f, int32_t K, const int32_t* idx,
+                               const float* grad_scores, float* dU, float* dI, void* stream);
+
+/* ------------------------------------------------------------------------- *
  * Diagnostics.
  * ------------------------------------------------------------------------- */
 const char* mips_status_string(int status);

@@ -215,6 +215,33 @@ int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stat
     return MIPS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free backward: one static array per device,
+// resolved once per device to its device address (the array's name in host
+// code is only a stand-in for the symbol).  Held until the process ends.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MIPS_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MIPS_ERR_UNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(MIPS_ERR_HIP, "scratch symbol has no aligned address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MIPS_OK;
+}
+
 }  // namespace mips
 
 using namespace mips;
@@ -268,17 +295,48 @@ int mips_profile_read(double* ms, int64_t* launches) {
     return rc;
 }
 
-int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
-                       int32_t K, const int32_t* idx, const float* grad_scores, float* dU,
-                       float* dI, void* stream) {
+static int backward_args(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
+                         int32_t K, const int32_t* idx, const float* grad_scores, const float* dU,
+                         const float* dI) {
     if (n_u < 1 || n_i < 1 || n_i >= ((int64_t)1 << 31) || n_u >= ((int64_t)1 << 31))
         return fail(MIPS_ERR_ARG, "n_u, n_i must be in [1, 2^31)");
     if (f < 1 || f > 4096) return fail(MIPS_ERR_ARG, "f must be in [1, 4096] (got %d)", f);
     if (K < 1) return fail(MIPS_ERR_ARG, "K must be >= 1 (got %d)", K);
     if (!U || !I || !idx || !grad_scores || !dU || !dI) return fail(MIPS_ERR_ARG, "null array pointer");
+    return MIPS_OK;
+}
+
+int mips_topk_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
+                       int32_t K, const int32_t* idx, const float* grad_scores, float* dU,
+                       float* dI, void* stream) {
+    const int rc = backward_args(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI);
+    if (rc != MIPS_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     PhaseTimer t(MIPS_PHASE_BACKWARD, s);
-    hipError_t e = launch_backward(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI, s);
+    hipError_t e = launch_backward(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "backward");
+    return MIPS_OK;
+}
+
+int mips_topk_backward_noalloc(const float* U, const float* I, int64_t n_u, int64_t n_i, int32_t f,
+                               int32_t K, const int32_t* idx, const float* grad_scores, float* dU,
+                               float* dI, void* stream) {
+    int rc = backward_args(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI);
+    if (rc != MIPS_OK) return rc;
+    const size_t need = backward_scratch_bytes(n_i, n_u * (int64_t)K);
+    if (need > MIPS_NOALLOC_SCRATCH_BYTES)
+        return fail(MIPS_ERR_UNSUPPORTED,
+                    "mips_topk_backward_noalloc: n_i = %lld and n_u K = %lld need %zu bytes of "
+                    "scratch; its static scratch holds %zu (12 n_i + 4 n_u K + 4 KiB at most)",
+                    (long long)n_i, (long long)(n_u * (int64_t)K), need,
+                    (size_t)MIPS_NOALLOC_SCRATCH_BYTES);
+    void* ptr = nullptr;
+    if ((rc = noalloc_scratch(&ptr)) != MIPS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    PhaseTimer t(MIPS_PHASE_BACKWARD, s);
+    // with n_u K >= 2^31 the direct scatter-add runs and needs no scratch
+    hipError_t e = launch_backward(U, I, n_u, n_i, f, K, idx, grad_scores, dU, dI,
+                                   need ? ptr : nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "backward");
     return MIPS_OK;
 }

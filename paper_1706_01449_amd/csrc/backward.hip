@@ -256,8 +256,19 @@ __global__ void __launch_bounds__(256) bwd_dI_kernel(const float* __restrict__ U
     }
 }
 
+// Scratch of the grouped dI path: counts, offsets, cursors, total, block
+// sums, grouped pairs (0 when the direct scatter-add is taken).
+static size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t backward_scratch_bytes(int64_t n_i, int64_t npairs) {
+    if (npairs >= ((int64_t)1 << 31)) return 0;
+    const int64_t nblk = (n_i + 1023) / 1024;
+    return 3 * al256b((size_t)n_i * 4) + 256 + al256b((size_t)nblk * 4) + (size_t)npairs * 4;
+}
+
 hipError_t launch_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int f, int K,
-                           const int32_t* idx, const float* G, float* dU, float* dI, hipStream_t s) {
+                           const int32_t* idx, const float* G, float* dU, float* dI,
+                           void* scratch_in, hipStream_t s) {
     hipError_t e = launch_zero(dI, (size_t)n_i * f * sizeof(float), s);
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)((n_u + 3) / 4);
@@ -266,14 +277,14 @@ hipError_t launch_backward(const float* U, const float* I, int64_t n_u, int64_t 
         topk_backward_kernel<<<dim3(blocks), dim3(256), 0, s>>>(U, I, n_u, n_i, f, K, idx, G, dU, dI);
         return hipGetLastError();
     }
-    // stream-ordered scratch: counts, offsets, cursors, total, block sums,
-    // grouped pairs
-    unsigned char* scratch = nullptr;
-    const size_t nb = (size_t)n_i * 4, ab = ((nb + 255) & ~(size_t)255);
+    // caller's scratch, else stream-ordered scratch
+    unsigned char* scratch = (unsigned char*)scratch_in;
+    const size_t nb = (size_t)n_i * 4, ab = al256b(nb);
     const int64_t nblk = (n_i + 1023) / 1024;
-    const size_t bb = ((size_t)nblk * 4 + 255) & ~(size_t)255;
-    const size_t bytes = 3 * ab + 256 + bb + (size_t)npairs * 4;
-    if ((e = hipMallocAsync((void**)&scratch, bytes, s)) != hipSuccess) return e;
+    const size_t bb = al256b((size_t)nblk * 4);
+    if (!scratch &&
+        (e = hipMallocAsync((void**)&scratch, backward_scratch_bytes(n_i, npairs), s)) != hipSuccess)
+        return e;
     unsigned int* cnt = (unsigned int*)scratch;
     unsigned int* off = (unsigned int*)(scratch + ab);
     unsigned int* cur = (unsigned int*)(scratch + 2 * ab);
@@ -292,6 +303,7 @@ hipError_t launch_backward(const float* U, const float* I, int64_t n_u, int64_t 
         bwd_dI_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(U, f, K, idx, G, grouped, total, dI);
         e = hipGetLastError();
     }
+    if (scratch_in) return e;
     const hipError_t e2 = hipFreeAsync(scratch, s);
     return e != hipSuccess ? e : e2;
 }

@@ -162,8 +162,12 @@ hipError_t launch_certify(const ScreenPlan& p, const ScreenArgs& a, hipStream_t 
 hipError_t launch_flag_all(int64_t n_u, int* uflag, int* flist, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_fallback(const ScreenPlan& p, const FallbackArgs& a, hipStream_t s);
 
+// scratch: backward_scratch_bytes(n_i, n_u K) bytes of device memory, or null
+// for stream-ordered scratch allocated and released on `s`
+size_t backward_scratch_bytes(int64_t n_i, int64_t npairs);
 hipError_t launch_backward(const float* U, const float* I, int64_t n_u, int64_t n_i, int f, int K,
-                           const int32_t* idx, const float* G, float* dU, float* dI, hipStream_t s);
+                           const int32_t* idx, const float* G, float* dU, float* dI,
+                           void* scratch, hipStream_t s);
 hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
                                  int64_t ni_elems, Ctrl* ctrl, hipStream_t s);
 

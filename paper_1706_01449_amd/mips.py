@@ -116,6 +116,8 @@ def lib():
                                       vp, vp]
     L.mips_topk_backward.restype = ctypes.c_int
     L.mips_topk_backward.argtypes = [vp, vp, c_i64, c_i64, c_i32, c_i32, vp, vp, vp, vp, vp]
+    L.mips_topk_backward_noalloc.restype = ctypes.c_int
+    L.mips_topk_backward_noalloc.argtypes = L.mips_topk_backward.argtypes
     L.mips_status_string.restype = ctypes.c_char_p
     L.mips_status_string.argtypes = [ctypes.c_int]
     L.mips_last_error_message.restype = ctypes.c_char_p
@@ -326,8 +328,11 @@ def optimus_topk(U: torch.Tensor, I: torch.Tensor, K: int, precision="bf16", n_c
     return idx, score, rep.as_dict()
 
 
-def topk_backward(U: torch.Tensor, I: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor):
-    """dU, dI of a loss on the top-K scores given dL/dS at the top-K positions."""
+def topk_backward(U: torch.Tensor, I: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor,
+                  noalloc: bool = False):
+    """dU, dI of a loss on the top-K scores given dL/dS at the top-K positions.
+    noalloc=True calls mips_topk_backward_noalloc (the library's static
+    scratch, no device allocation inside the call)."""
     U = _mat(U, "U")
     I = _mat(I, "I")
     n_u, f = U.shape
@@ -339,8 +344,9 @@ def topk_backward(U: torch.Tensor, I: torch.Tensor, idx: torch.Tensor, grad_scor
         raise ValueError("idx and grad_scores must be n_u x K")
     dU = torch.empty_like(U)
     dI = torch.empty_like(I)
-    _check(lib().mips_topk_backward(U.data_ptr(), I.data_ptr(), n_u, n_i, f, K, idx.data_ptr(),
-                                    g.data_ptr(), dU.data_ptr(), dI.data_ptr(), _stream(U.device)))
+    fn = lib().mips_topk_backward_noalloc if noalloc else lib().mips_topk_backward
+    _check(fn(U.data_ptr(), I.data_ptr(), n_u, n_i, f, K, idx.data_ptr(), g.data_ptr(),
+              dU.data_ptr(), dI.data_ptr(), _stream(U.device)))
     return dU, dI
 
 
