@@ -81,6 +81,9 @@ def log(msg):
 
 
 def time_path(mips, torch, Ut, It, K, prec, steps, warmup):
+    """Times `steps` back-to-back calls: the whole bracket by the host clock
+    (synchronised on both sides) and each call by a HIP event pair on the
+    call's stream; the library's own events give the per-kernel durations."""
     ws = torch.empty(mips.lib().mips_bmm_topk_workspace_size(Ut.shape[0], It.shape[0],
                                                               Ut.shape[1], K,
                                                               mips.PRECISIONS[prec]),
@@ -89,30 +92,62 @@ def time_path(mips, torch, Ut, It, K, prec, steps, warmup):
         mips.bmm_topk(Ut, It, K, prec, workspace=ws)
     torch.cuda.synchronize()
     mips.profile_read()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     mips.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for e0, e1 in ev:
+        e0.record()
         out = mips.bmm_topk(Ut, It, K, prec, workspace=ws)
+        e1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     mips.profile_enable(False)
     phases = mips.profile_read()
+    calls = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    per_call = {"median": calls[len(calls) // 2], "min": calls[0], "mean": sum(calls) / len(calls)}
     _, _, st = mips.bmm_topk(Ut, It, K, prec, stats=True, workspace=ws)
-    return (t1 - t0) / steps, phases, st, out
+    return (t1 - t0) / steps, phases, st, out, per_call
 
 
 def timed(torch, fn, reps):
-    """Median wall time of fn() in ms, synchronised (inputs resident)."""
+    """Median and min per-call time in ms: HIP events on the current stream
+    around each call (inputs resident)."""
     ts = []
     for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0.record()
         fn()
+        e1.record()
         torch.cuda.synchronize()
-        ts.append((time.perf_counter() - t0) * 1e3)
+        ts.append(e0.elapsed_time(e1))
     ts.sort()
     return ts[len(ts) // 2]
+
+
+def k_sweep(mips, torch, Ut, It, n_u):
+    """users/s of the bfloat16 and float32 screens at K in {1, 5, 50}, and the
+    E4M3 screen's exact-path users at K = 50."""
+    out = {}
+    for prec, steps in (("bf16", 10), ("fp32", 4)):
+        for K in (1, 5, 50):
+            log(f"k sweep: {prec} K={K}")
+            t, ph, st, _, pc = time_path(mips, torch, Ut, It, K, prec, steps, 1)
+            out[f"{prec}_K{K}"] = {"users_per_s": n_u / t, "ms_per_call_median": pc["median"],
+                                   "ms_per_call_min": pc["min"],
+                                   "screen_ms": ph["screen"][0] / max(1, ph["screen"][1]),
+                                   "candidates_per_user": st["candidates_total"] / n_u,
+                                   "exact_path_users": st["overflow_users"]}
+    log("k sweep: fp8 K=50")
+    t, ph, st, _, pc = time_path(mips, torch, Ut, It, 50, "fp8", 4, 1)
+    out["fp8_K50"] = {"users_per_s": n_u / t, "ms_per_call_median": pc["median"],
+                      "candidates_per_user": st["candidates_total"] / n_u,
+                      "exact_path_users": st["overflow_users"],
+                      "exact_path_fraction": st["overflow_users"] / n_u}
+    return out
 
 
 def extras(mips, torch, np, mipsgen, oracle_topk):
@@ -140,9 +175,16 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
         mips.profile_enable(False)
         qph = {k: v[0] / max(1, v[1]) for k, v in mips.profile_read().items() if v[1]}
         idx, score, st = ix.query(10, "bf16", stats=True)
+        tq32 = timed(torch, lambda: ix.query(10, "fp32"), 3)
         users = mipsgen.sample_users(U.shape[0], 200, seed=C)
         ri, _ = oracle_topk.topk(U[users], I, 10)
-        mx[f"C{C}"] = {"build_ms": tb, "query_ms": tq, "end_to_end_ms": tb + tq,
+        walk_ms = qph.get("walk", 0.0)
+        useful = 2.0 * U.shape[1] * st["items_scored"]          # 2 f sum_u w_u
+        mx[f"C{C}"] = {"build_ms": tb, "query_ms": tq, "query_fp32_ms": tq32, "end_to_end_ms": tb + tq,
+                       "tiles_per_user": st["mean_items_visited"] / 32.0,
+                       "walk_useful_tflops": useful / (walk_ms * 1e-3) / 1e12 if walk_ms else None,
+                       "walk_mfma_frac_bf16": (useful / (walk_ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]
+                                               if walk_ms else None),
                        "users_per_s_query": U.shape[0] / (tq * 1e-3),
                        "users_per_s_end_to_end": U.shape[0] / ((tb + tq) * 1e-3),
                        "mean_items_visited": st["mean_items_visited"],
@@ -240,30 +282,60 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
     tbk = timed(torch, lambda: mips.topk_backward(Ut, It, idx, G), 10)
     pairs = U.shape[0] * 32
     bytes_alg = pairs * 64 * 4 * 2 + U.shape[0] * 64 * 4 * 2 + I.shape[0] * 64 * 4
+    # dI issues one float32 atomic per factor per run of equal items in each
+    # wave's 64 grouped pairs (pairs sorted by item)
+    it_sorted = np.sort(idx.cpu().numpy().reshape(-1), kind="stable")
+    starts = np.ones(it_sorted.size, dtype=bool)
+    starts[1:] = it_sorted[1:] != it_sorted[:-1]
+    starts[::64] = True
+    atomics = int(starts.sum()) * 64
     out["grad_65536x100000_f64_K32"] = {
         "forward_ms": tf, "backward_ms": tbk,
         "backward_pairs_per_s": pairs / (tbk * 1e-3),
-        "backward_algorithmic_GBps": bytes_alg / (tbk * 1e-3) / 1e9}
+        "backward_algorithmic_GBps": bytes_alg / (tbk * 1e-3) / 1e9,
+        "backward_dI_atomics": atomics,
+        "backward_dI_atomics_per_s": atomics / (tbk * 1e-3),
+        "direct_scatter_atomics": pairs * 64}
     return out
 
 
-def cpu_baseline(U, I, K, seconds_target=15.0):
-    """The oracle as it stands, on a bounded user sample, all host cores."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(U, I, K, seconds_target=12.0, seconds_one=8.0):
+    """The oracle as it stands, on bounded user samples: all host cores, and
+    one core (the paper's setting)."""
     from oracle import topk as oracle_topk
     oracle_topk.build(force=False)
     cores = oracle_topk.num_threads()
-    probe = 256
-    t0 = time.perf_counter()
-    oracle_topk.topk(U[:probe], I, K)
-    dt = time.perf_counter() - t0
-    n = int(min(U.shape[0], max(probe, probe * seconds_target / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    oracle_topk.topk(U[:n], I, K)
-    dt = time.perf_counter() - t0
+
+    def rate(threads, target):
+        probe = 256 if threads != 1 else 32
+        t0 = time.perf_counter()
+        oracle_topk.topk(U[:probe], I, K, nthreads=threads)
+        dt = time.perf_counter() - t0
+        n = int(min(U.shape[0], max(probe, probe * target / max(dt, 1e-6))))
+        t0 = time.perf_counter()
+        oracle_topk.topk(U[:n], I, K, nthreads=threads)
+        dt = time.perf_counter() - t0
+        return n, dt
+
+    n, dt = rate(0, seconds_target)
+    n1, dt1 = rate(1, seconds_one)
     return {"value": n / dt, "unit": "users/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} of {U.shape[0]} users x all {I.shape[0]} items, f={U.shape[1]}, "
-                      f"K={K}, float64 keys + sorted K-list, {dt:.1f} s"}
+                      f"K={K}, float64 keys + sorted K-list, {dt:.1f} s on {cores} threads",
+            "cpu_model": cpu_model(),
+            "one_core": {"value": n1 / dt1, "unit": "users/s", "cores": 1,
+                         "sample": f"first {n1} users, {dt1:.1f} s"}}
 
 
 def main():
@@ -310,13 +382,14 @@ def main():
     torch.cuda.synchronize()
 
     log(f"timing {args.precision} screen")
-    t_main, ph_main, st_main, out = time_path(mips, torch, Ut, It, K, args.precision,
-                                              args.steps, args.warmup)
+    t_main, ph_main, st_main, out, pc_main = time_path(mips, torch, Ut, It, K, args.precision,
+                                                       args.steps, args.warmup)
     fp32 = None
     if not args.no_fp32 and args.precision != "fp32":
         log("timing fp32 screen")
-        t32, ph32, st32, _ = time_path(mips, torch, Ut, It, K, "fp32", max(3, args.steps // 4), 1)
+        t32, ph32, st32, _, pc32 = time_path(mips, torch, Ut, It, K, "fp32", max(3, args.steps // 4), 1)
         fp32 = {"users_per_s": n_u / t32, "ms_per_step": t32 * 1e3,
+                "ms_per_call_median": pc32["median"], "ms_per_call_min": pc32["min"],
                 "screen_ms": ph32["screen"][0] / max(1, ph32["screen"][1])}
 
     # parity spot check on sampled users
@@ -350,12 +423,16 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(), "kernel": "screen_kernel",
                      "kernel_ms": scr_ms},
+        "ms_per_call": pc_main,
+        "users_per_s_median_call": n_u / (pc_main["median"] * 1e-3),
         "phases_ms": {k: v[0] / max(1, v[1]) for k, v in ph_main.items() if v[1]},
         "fp32_screen": fp32,
         "index_match_sampled": match,
         "max_score_err_sampled": max_score_err,
         "stats": st_main,
     }
+    if not args.no_extras:
+        line["k_sweep"] = k_sweep(mips, torch, Ut, It, n_u)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(U, I, K)

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -80,7 +81,7 @@ static std::atomic<int> g_dbg_cand_cap{0}, g_dbg_certify{0};
 int debug_cand_cap() { return g_dbg_cand_cap.load(std::memory_order_relaxed); }
 int debug_certify_kernel() { return g_dbg_certify.load(std::memory_order_relaxed); }
 
-bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t, ScreenPlan* out) {
+bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, bool stops, ScreenPlan* out) {
     ScreenPlan p;
     p.prec = prec;
     p.f = f;
@@ -107,7 +108,7 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t,
     }
     p.nch = p.NCH;
     p.KM = K <= 1 ? 1 : (K <= 8 ? 8 : (K <= 10 ? 10 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64))));
-    p.UB = ub_for(prec, p.KM, p.NCH);
+    p.UB = ub_for(prec, p.KM, p.NCH, stops);
     // Candidate slots per lane (half a user's items): room for the K-list
     // entries plus the items that pass before the threshold settles; the
     // coarser E4M3 screen keeps several times more.
@@ -172,7 +173,7 @@ static BmmLayout bmm_layout(const ScreenPlan& p) {
             L.Eorigb = take((size_t)p.n_i * 4);
         }
         L.cnt = take((size_t)p.n_ublk * 64 * 4);
-        L.cand = take((size_t)p.n_ublk * p.cap * 64 * 8);
+        L.cand = take(cand_bytes(p.n_ublk, p.cap));
     }
     L.fbkeys = take((size_t)p.fb_grid * p.n_i * 8);
     L.total = o;
@@ -344,9 +345,12 @@ int mips_topk_backward_noalloc(const float* U, const float* I, int64_t n_u, int6
 size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t K,
                                     int32_t precision) {
     if (check_common(n_u, n_i, f, K, precision) != MIPS_OK) return 0;
-    ScreenPlan p;
-    make_screen_plan(n_u, n_i, f, K, screen_prec(precision), 0, &p);
-    return bmm_layout(p).total;
+    // one size for both sweeps (their plans may hold different block counts)
+    const int sp = screen_prec(precision);
+    ScreenPlan p0, p1;
+    make_screen_plan(n_u, n_i, f, K, sp, false, &p0);
+    make_screen_plan(n_u, n_i, f, K, sp, true, &p1);
+    return std::max(bmm_layout(p0).total, bmm_layout(p1).total);
 }
 
 int mips_debug_set(int32_t knob, int32_t value) {
@@ -373,7 +377,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
     const bool casc = cascade_of(precision);
     precision = screen_prec(precision);
     ScreenPlan p;
-    make_screen_plan(n_u, n_i, f, K, precision, 0, &p);
+    make_screen_plan(n_u, n_i, f, K, precision, prune != 0, &p);
     const BmmLayout L = bmm_layout(p);
     if (!workspace || workspace_bytes < L.total)
         return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", L.total, workspace_bytes);

@@ -62,8 +62,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             unorm = sqrt(unorm);
         }
         // the user's two lists (lanes n and n+32 of its screen wave), lane-major
-        const int2* list0 = a.cand + ((ublk << 6) + n) * (int64_t)a.cap;
-        const int2* list1 = a.cand + ((ublk << 6) + n + 32) * (int64_t)a.cap;
+        const int64_t base0 = cand_at(ublk, n, 0, a.cap), base1 = cand_at(ublk, n + 32, 0, a.cap);
         for (int j0 = g; j0 < tot; j0 += 4 * G) {
             int2 e[4];
             float Ci[4], Gi[4];
@@ -71,7 +70,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             for (int q = 0; q < 4; ++q) {
                 const int j = j0 + q * G;
                 e[q] = make_int2(0, -1);
-                if (j < tot) e[q] = (j < m0) ? list0[j] : list1[j - m0];
+                if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j : base1 + (j - m0)];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -265,8 +264,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     double tau64 = (double)us.w;       // kept pairs: key >= tau64
     float thr = us.w;                  // candidates: upper bound >= thr (thr <= tau64)
     const int tot = c0 + c1;
-    const int2* list0 = a.cand + ((ublk << 6) + n) * (int64_t)a.cap;
-    const int2* list1 = a.cand + ((ublk << 6) + n + 32) * (int64_t)a.cap;
+    const int64_t base0 = cand_at(ublk, n, 0, a.cap), base1 = cand_at(ublk, n + 32, 0, a.cap);
     __syncthreads();
     double unorm = 0.0;   // ||u||, for the relative error statistic only
     if (a.want_stats) {
@@ -473,7 +471,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     for (int base = 0; base < tot; base += 64) {
         const int j = base + lane;
         int2 e = make_int2(0, -1);
-        if (j < tot) e = (j < c0) ? list0[j] : list1[j - c0];
+        if (j < tot) e = a.cand[(j < c0) ? base0 + j : base1 + (j - c0)];
         bool keep = false;
         if (e.y >= 0) {
             const float eb = fmaf(us.x, a.Corig[e.y], fmaf(us.y, a.Gorig[e.y], us.z));

@@ -21,15 +21,28 @@ inline bool cascade_of(int p) { return p == PREC_FP8_CASCADE; }
 inline bool valid_prec(int p) { return p >= PREC_FP32 && p <= PREC_FP8_CASCADE; }
 
 // User blocks of 32 per screen wave.  Each user block holds its operand
-// registers, two accumulator sets (software pipeline) and a KM-entry K-list,
-// so fewer blocks fit when the list or the operands grow: two blocks up to a
+// registers, an accumulator tile and a KM-entry K-list.  The bfloat16 brute
+// force takes four blocks (128 users: each item tile loaded once per 128
+// users) up to 64 factors and 16 list entries (E4M3, with its hundreds of
+// candidates per user, was measured slower so); otherwise two blocks up to a
 // 32-entry list, except for the float32 screen past 16 entries or 32 chunks
-// and the bfloat16 screen with a 32-entry list over 8 chunks.
-__host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap) {
-    return prec == PREC_FP32
-               ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
-               : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1));
+// and the bfloat16 screen with a 32-entry list over 8 chunks.  Sweeps with a
+// stop test (the walk, the norm-pruned brute force) keep at most two blocks,
+// since a wave runs until its slowest user stops.
+__host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap, bool stops) {
+    return (!stops && prec == PREC_BF16 && km <= 16 && nch_cap <= 4)
+               ? 4
+               : (prec == PREC_FP32
+                      ? ((km <= 16 && nch_cap <= 32) ? 2 : 1)
+                      : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1)));
 }
+
+// Candidate lists, lane-major: entry j of lane l of user block blk sits at
+// ((blk 64) + l) cap + j (each lane appends to a list of its own).
+__host__ __device__ inline int64_t cand_at(int64_t blk, int lane, int j, int cap) {
+    return ((blk * 64) + lane) * (int64_t)cap + j;
+}
+inline size_t cand_bytes(int64_t n_ublk, int cap) { return (size_t)n_ublk * 64 * cap * 8; }
 
 // Device-resident control block of one call.  Zeroed at the start of every
 // call by a fill kernel (never by a memset node, so callers may capture the
@@ -201,7 +214,7 @@ int debug_certify_kernel();
 int finish_stats(Ctrl* dctrl, hipStream_t s, int64_t n_u, int64_t n_i, mips_stats* stats);
 
 // Plan selection (host only).
-bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, int64_t n_waves_override,
+bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, bool stops,
                       ScreenPlan* out);
 
 }  // namespace mips

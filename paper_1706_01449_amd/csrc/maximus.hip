@@ -810,7 +810,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         TRY(launch_zero(tctrl, 3 * sizeof(Ctrl), s), "zero");
         for (int prec = 0; prec < 3; ++prec) {
             ScreenPlan p;
-            make_screen_plan(n_u, n_i, f, 1, prec, 0, &p);
+            make_screen_plan(n_u, n_i, f, 1, prec, true, &p);
             const size_t esz = prec == PREC_FP32 ? 4 : (prec == PREC_BF16 ? 2 : 1);
             unsigned char* q = nullptr;
             TRY(dalloc(ix, &q, (size_t)n_i * p.f_pad * esz), "alloc screen rows");
@@ -889,25 +889,50 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
 
 void mips_maximus_free(mips_maximus_index* index) { free_index(index); }
 
-static int64_t walk_cap_check(const ScreenPlan& p) { return p.cap; }
+}  // extern "C"
+
+namespace {
+
+// Workspace of a query of the index's own users: one layout for the size
+// function and the query.
+struct IndexQueryLayout {
+    size_t ctrl, uflag, zero_end, flist, uscal, cnt, cand, fbkeys, total;
+};
+
+IndexQueryLayout index_query_layout(const mips_maximus_index* ix, const ScreenPlan& p) {
+    IndexQueryLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += (b + 255) & ~(size_t)255; return r; };
+    L.ctrl = take(sizeof(Ctrl));
+    L.uflag = take((size_t)ix->n_u * 4);
+    L.zero_end = o;
+    L.flist = take((size_t)ix->n_u * 4);
+    L.uscal = take((size_t)ix->n_u * 16);
+    L.cnt = take((size_t)p.n_ublk * 64 * 4);
+    L.cand = take(cand_bytes(p.n_ublk, p.cap));
+    L.fbkeys = take((size_t)p.fb_grid * ix->n_i * 8);
+    L.total = o;
+    return L;
+}
+
+// The plan of a query of the index's own users (walk tiles of the plan's
+// block count).
+ScreenPlan index_query_plan(const mips_maximus_index* ix, int32_t K, int32_t precision) {
+    ScreenPlan p;
+    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, screen_prec(precision), true, &p);
+    p.n_waves = p.fast ? ix->ntiles[ub_slot(p.UB)] : 0;
+    p.n_ublk = p.n_waves * p.UB;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
 
 size_t mips_maximus_query_workspace_size(const mips_maximus_index* ix, int32_t K, int32_t precision) {
     if (!ix || K < 1 || (int64_t)K > ix->n_i || K > kFallbackMaxK || !valid_prec(precision))
         return 0;
-    ScreenPlan p;
-    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
-    const int64_t nw = p.fast ? ix->ntiles[ub_slot(p.UB)] : 0;
-    const int64_t n_ublk = nw * p.UB;
-    size_t o = 0;
-    auto take = [&](size_t b) { o += (b + 255) & ~(size_t)255; };
-    take(sizeof(Ctrl));
-    take((size_t)ix->n_u * 4);          // uflag
-    take((size_t)ix->n_u * 4);          // flist
-    take((size_t)ix->n_u * 16);         // uscal
-    take((size_t)n_ublk * 64 * 4);      // cnt
-    take((size_t)n_ublk * 64 * walk_cap_check(p) * 8);  // cand
-    take((size_t)p.fb_grid * ix->n_i * 8);              // fallback keys
-    return o;
+    return index_query_layout(ix, index_query_plan(ix, K, precision)).total;
 }
 
 }  // extern "C"
@@ -954,7 +979,7 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
     if (casc && ix->qrow[PREC_BF16]) {
         // bfloat16 rows of the index for the certification cascade
         ScreenPlan pb;
-        make_screen_plan(1, ix->n_i, ix->f, 1, PREC_BF16, 0, &pb);
+        make_screen_plan(1, ix->n_i, ix->f, 1, PREC_BF16, true, &pb);
         a.qrow_b = ix->qrow[PREC_BF16];
         a.Gorig_b = ix->Gorig[PREC_BF16];
         a.maxb = &ix->prep_ctrl[PREC_BF16].cmax_bits;
@@ -1035,7 +1060,7 @@ QueryLayout query_layout(const mips_maximus_index* ix, const ScreenPlan& p, int6
     L.qassign = take((size_t)n_q * 4);
     L.sorted = take((size_t)n_q * 4);
     L.cnt = take((size_t)n_ublk * 64 * 4);
-    L.cand = take((size_t)n_ublk * 64 * p.cap * 8);
+    L.cand = take(cand_bytes(n_ublk, p.cap));
     L.fbkeys = take((size_t)p.fb_grid * ix->n_i * 8);
     L.total = o;
     return L;
@@ -1055,23 +1080,20 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
         return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
     if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    ScreenPlan p;
-    make_screen_plan(ix->n_u, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
+    const ScreenPlan p = index_query_plan(ix, K, precision);
     const int slot = ub_slot(p.UB);
-    p.n_waves = p.fast ? ix->ntiles[slot] : 0;
-    p.n_ublk = p.n_waves * p.UB;
-
+    const IndexQueryLayout L = index_query_layout(ix, p);
+    if (L.total > workspace_bytes)
+        return fail(MIPS_ERR_WORKSPACE, "workspace layout needs %zu bytes (got %zu)", L.total, workspace_bytes);
     char* ws = (char*)workspace;
-    size_t o = 0;
-    auto take = [&](size_t b) { size_t r = o; o += (b + 255) & ~(size_t)255; return ws + r; };
-    Ctrl* ctrl = (Ctrl*)take(sizeof(Ctrl));
-    int* uflag = (int*)take((size_t)ix->n_u * 4);
-    const size_t zero_bytes = o;
-    int* flist = (int*)take((size_t)ix->n_u * 4);
-    float4* uscal = (float4*)take((size_t)ix->n_u * 16);
-    int* cnt = (int*)take((size_t)p.n_ublk * 64 * 4);
-    int2* cand = (int2*)take((size_t)p.n_ublk * 64 * p.cap * 8);
-    double* fbkeys = (double*)take((size_t)p.fb_grid * ix->n_i * 8);
+    Ctrl* ctrl = (Ctrl*)(ws + L.ctrl);
+    int* uflag = (int*)(ws + L.uflag);
+    const size_t zero_bytes = L.zero_end;
+    int* flist = (int*)(ws + L.flist);
+    float4* uscal = (float4*)(ws + L.uscal);
+    int* cnt = (int*)(ws + L.cnt);
+    int2* cand = (int2*)(ws + L.cand);
+    double* fbkeys = (double*)(ws + L.fbkeys);
     hipError_t e;
     if ((e = launch_zero(ws, zero_bytes, s)) != hipSuccess) return hip_fail(e, "zero");
     rc = walk_certify_fallback(ix, p, screen_prec(precision), cascade_of(precision), ix->U, ix->n_u, ix->tiles[slot], ix->sorted_users,
@@ -1095,7 +1117,7 @@ size_t mips_maximus_query_users_workspace_size(const mips_maximus_index* ix, int
         K > kFallbackMaxK || !valid_prec(precision))
         return 0;
     ScreenPlan p;
-    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
+    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), true, &p);
     return query_layout(ix, p, n_q).total;
 }
 
@@ -1113,7 +1135,7 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     if (((uintptr_t)workspace & 255) != 0) return fail(MIPS_ERR_ARG, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     ScreenPlan p;
-    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), 0, &p);
+    make_screen_plan(n_q, ix->n_i, ix->f, K, screen_prec(precision), true, &p);
     const QueryLayout L = query_layout(ix, p, n_q);
     p.n_waves = L.max_tiles;
     p.n_ublk = p.n_waves * p.UB;

@@ -31,6 +31,8 @@
 // float32 rounding of every threshold and bound computed here.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -253,19 +255,26 @@ __host__ __device__ constexpr int warm_sets(int km) {
 }
 
 // Certification runs at the end of the screen kernel when the K-list fits a
-// small sorted register list, two user blocks keep every lane busy (one user
-// per lane), and the screen keeps few candidates per user (not E4M3, whose
-// hundreds of candidates per user make one lane per user too slow; there the
-// separate kernel spreads a user over 16 or 64 lanes).
+// small sorted register list, an even number of user blocks keeps every lane
+// busy (one user per lane and pass), and the screen keeps few candidates per
+// user (not E4M3, whose hundreds of candidates per user make one lane per
+// user too slow; there the separate kernel spreads a user over 16 or 64
+// lanes).
 __host__ __device__ constexpr bool fused_certify(int prec, int km, int ub) {
-    return prec != PREC_FP8 && km <= 16 && ub == 2;
+    return prec != PREC_FP8 && km <= 16 && ub % 2 == 0;
 }
+
 
 // ---------------------------------------------------------------------------
 // The screen kernel.
 // ---------------------------------------------------------------------------
-template <int PREC, int KM, int NCH, int UB, bool WALK>
+// Sweep modes: the brute force, the norm-pruned brute force (stop test over
+// the suffix maxima of the norm-ordered tiles) and the Maximus walk.
+constexpr int kSweepBrute = 0, kSweepPruned = 1, kSweepWalk = 2;
+
+template <int PREC, int KM, int NCH, int UB, int MODE>
 __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
+    constexpr bool WALK = MODE == kSweepWalk;
     typedef Prec<PREC> P;
     typedef typename P::Op Op;
     constexpr int E = P::E;
@@ -286,11 +295,31 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     Op bu[UB][NCH];
     float Au[UB], Bu[UB], slk[UB], tau[UB], tauf[UB], Nup[UB];
     int ustop[UB];                // walk: tiles visited before the user stopped
-    float lst[UB][KM];
+    // K-lists: registers, or LDS (lane-major, conflict-free) where they or
+    // the operands would take most of the registers (four user blocks, 32
+    // operand registers per block, lists of 32 or more entries); the lists
+    // are touched only when a tile has hits.
+    constexpr int OPR = NCH * (PREC == PREC_FP32 ? 1 : (PREC == PREC_BF16 ? 4 : 8));
+    constexpr bool LDSL = UB >= 4 || OPR >= 32 || KM >= 32;
+    float lst[UB][LDSL ? 1 : KM];
+    __shared__ float s_lst[LDSL ? UB * KM * kWave : 1];
+    auto list_load = [&](int ub, float (&L)[KM]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < KM; ++q) {
+            if constexpr (LDSL) L[q] = s_lst[(ub * KM + q) * kWave + lane];
+            else L[q] = lst[ub][q];
+        }
+    };
+    auto list_store = [&](int ub, const float (&L)[KM]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < KM; ++q) {
+            if constexpr (LDSL) s_lst[(ub * KM + q) * kWave + lane] = L[q];
+            else lst[ub][q] = L[q];
+        }
+    };
     int cnt[UB], uscale[UB];
     bool dgn[UB];                 // degenerate user: already on the exact path
     bool act[UB];
-    int2* cptr[UB];
 
     // ---- prologue: load, quantise and measure this wave's users ----------
 #pragma unroll
@@ -389,8 +418,6 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         tau[ub] = ninf;
         cnt[ub] = 0;
         ustop[ub] = -1;
-        cptr[ub] = a.cand + (((w * UB + ub) << 6) + lane) * (int64_t)a.cap;   // lane-major lists
-        list_reset(lst[ub], a.K);
     }
 
     // list slot of the ceil(K/2)-th largest real entry (KM-K +inf pads first)
@@ -427,24 +454,24 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         }
     };
 
-    // Score tile: acc[ub] = items (rows) x users (columns); rows past the
-    // last item are set to -inf.
-    auto score_tile = [&](int b, const Op (&ai)[NCH], int iscale, floatx16_t (&acc)[UB])
-        __attribute__((always_inline)) {
+    // Scores of user block ub on tile b: items (rows) x users (columns).  Rows
+    // past the last item hold zero operands (score 0); the warm-up sets them
+    // to -inf here, the sweep drops them where it looks at rows (their item
+    // index is -1), so its common path carries no test for them.
+    const int n_full = (int)(a.n_i / kTile);   // tiles without rows past the last item
+    auto score_one = [&](int b, const Op (&ai)[NCH], int iscale, int ub) __attribute__((always_inline))
+        -> floatx16_t {
+        floatx16_t acc = {};
 #pragma unroll
-        for (int ub = 0; ub < UB; ++ub) {
-            floatx16_t z = {};
-            acc[ub] = z;
+        for (int c = 0; c < NCH; ++c) acc = P::mma(ai[c], bu[ub][c], acc, iscale, uscale[ub]);
+        return acc;
+    };
+    auto mask_rows = [&](int b, floatx16_t& acc) __attribute__((always_inline)) {
+        if (b >= n_full) {
+            const int rem = (int)(a.n_i - (int64_t)b * kTile);   // rows of tile b holding items
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                acc[ub] = P::mma(ai[c], bu[ub][c], acc[ub], iscale, uscale[ub]);
-        }
-        if ((int64_t)(b + 1) * kTile > a.n_i) {
-#pragma unroll
-            for (int ub = 0; ub < UB; ++ub)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if ((int64_t)b * kTile + 8 * (r >> 2) + 4 * h + (r & 3) >= a.n_i) acc[ub][r] = ninf;
+            for (int r = 0; r < 16; ++r)
+                if (8 * (r >> 2) + 4 * h + (r & 3) >= rem) acc[r] = ninf;
         }
     };
 
@@ -454,12 +481,12 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // largest of their lower bounds (over the user's two lanes) is a valid
     // lower bound on the user's K-th largest key.  The leading tiles hold the
     // largest-norm items (brute force) or the best-bound items (walk).
-    {
-        float gm[UB][S * 16];
+    // One user block at a time, so that only one block's slot maxima are live.
 #pragma unroll
-        for (int ub = 0; ub < UB; ++ub)
+    for (int ub = 0; ub < UB; ++ub) {
+        float gm[S * 16];
 #pragma unroll
-            for (int q = 0; q < S * 16; ++q) gm[ub][q] = ninf;
+        for (int q = 0; q < S * 16; ++q) gm[q] = ninf;
         for (int rd = 0; rd < a.warm_rounds; ++rd) {
 #pragma unroll
             for (int sidx = 0; sidx < S; ++sidx) {
@@ -470,90 +497,90 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     float2 bmw;
                     float2 cgw;
                     load_tile(b, ai, it, sc, bmw, cgw);
-                    floatx16_t acc[UB];
-                    score_tile(b, ai, sc, acc);
+                    floatx16_t acc = score_one(b, ai, sc, ub);
+                    mask_rows(b, acc);
 #pragma unroll
-                    for (int ub = 0; ub < UB; ++ub)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            gm[ub][sidx * 16 + r] = vmax(gm[ub][sidx * 16 + r], acc[ub][r]);
+                    for (int r = 0; r < 16; ++r) gm[sidx * 16 + r] = vmax(gm[sidx * 16 + r], acc[r]);
                 }
             }
         }
+        // every warm-up item has e <= A Cmax + B Gmax + slack
+        const float ew = fmaf(Au[ub], Cmax, fmaf(Bu[ub], Gmax, slk[ub]));
+        float L[KM];
+        list_reset(L, a.K);
 #pragma unroll
-        for (int ub = 0; ub < UB; ++ub) {
-            // every warm-up item has e <= A Cmax + B Gmax + slack
-            const float ew = fmaf(Au[ub], Cmax, fmaf(Bu[ub], Gmax, slk[ub]));
-#pragma unroll
-            for (int q = 0; q < S * 16; ++q) list_insert(lst[ub], gm[ub][q] - ew);
-            tau[ub] = list_tau(lst[ub], hidx, k_is_km);
-            list_reset(lst[ub], a.K);
-            tauf[ub] = act[ub] ? tau[ub] : pinf;
-        }
+        for (int q = 0; q < S * 16; ++q) list_insert(L, gm[q] - ew);
+        tau[ub] = list_tau(L, hidx, k_is_km);
+        list_reset(L, a.K);
+        list_store(ub, L);
+        tauf[ub] = act[ub] ? tau[ub] : pinf;
     }
 
-    // Streaming top-K over tile b; returns false once every user of a walk
-    // wave has stopped.
-    auto epi_tile = [&](int b, floatx16_t (&acc)[UB], int item, float2 bm, float2 cg)
-        __attribute__((always_inline)) -> bool {
+    // Streaming top-K over one user block of one tile: a wave-wide test of
+    // the lanes' tile maxima against tau_u - e_tile(u); only when some lane
+    // passes are the row groups and rows walked.
+    auto test_block = [&](int ub, const floatx16_t& sc, int item, float2 bm, float2 cg)
+        __attribute__((always_inline)) {
+        const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
+        const float thr = tauf[ub] - ee;
+        // maxima of the four row groups {4g .. 4g+3}, then of the tile
+        float gm4[4];
 #pragma unroll
-        for (int ub = 0; ub < UB; ++ub) {
-            const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
-            const float thr = tauf[ub] - ee;
-            // maxima of the four row groups {4g .. 4g+3}, then of the tile
-            float gm4[4];
+        for (int g = 0; g < 4; ++g)
+            gm4[g] = vmax(vmax(sc[4 * g], sc[4 * g + 1]), vmax(sc[4 * g + 2], sc[4 * g + 3]));
+        const float m = vmax(vmax(gm4[0], gm4[1]), vmax(gm4[2], gm4[3]));
+        if (!ballot(m >= thr)) return;
+        float L[KM];
+        list_load(ub, L);
+        // a group is walked only when some lane's group maximum passes
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                gm4[g] = vmax(vmax(acc[ub][4 * g], acc[ub][4 * g + 1]),
-                              vmax(acc[ub][4 * g + 2], acc[ub][4 * g + 3]));
-            const float m = vmax(vmax(gm4[0], gm4[1]), vmax(gm4[2], gm4[3]));
-            if (ballot(m >= thr)) {
-                // a group is walked only when some lane's group maximum passes
+        for (int g = 0; g < 4; ++g) {
+            if (!ballot(gm4[g] >= thr)) continue;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    if (!ballot(gm4[g] >= thr)) continue;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int r = 4 * g + q;
-                        const float v = acc[ub][r];
-                        bool hit = (v >= thr) && (v > ninf);
-                        if (ballot(hit)) {
-                            // item index of output row 8g + 4h + q, held by lane (row)
-                            const int row = 8 * g + 4 * h + q;
-                            const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
-                            float lb = v - ee;
-                            if constexpr (pair_bound_walk(WALK, PREC, KM, NCH)) {
-                                // walk tiles mix item norms, so the tile's
-                                // bound is loose: test the pair's own bound
-                                const float ci = __int_as_float(
-                                    __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.x)));
-                                const float gi = __int_as_float(
-                                    __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.y)));
-                                const float ei = fmaf(Au[ub], ci, fmaf(Bu[ub], gi, slk[ub]));
-                                hit = hit && (v + ei >= tauf[ub]);
-                                lb = v - ei;
-                            }
-                            if (hit) {
-                                list_insert(lst[ub], lb);
-                                if (cnt[ub] < a.cap)
-                                    cptr[ub][cnt[ub]] = make_int2(__float_as_int(v), orig);
-                                cnt[ub] += 1;
-                            }
-                        }
+            for (int q = 0; q < 4; ++q) {
+                const float v = sc[4 * g + q];
+                bool hit = (v >= thr) && (v > ninf);
+                if (ballot(hit)) {
+                    // item index of output row 8g + 4h + q, held by lane (row);
+                    // -1 for rows past the last item
+                    const int row = 8 * g + 4 * h + q;
+                    const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
+                    hit = hit && orig >= 0;
+                    float lb = v - ee;
+                    if constexpr (pair_bound_walk(WALK, PREC, KM, NCH)) {
+                        // walk tiles mix item norms, so the tile's bound is
+                        // loose: test the pair's own bound
+                        const float ci = __int_as_float(
+                            __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.x)));
+                        const float gi = __int_as_float(
+                            __builtin_amdgcn_ds_bpermute(row << 2, __float_as_int(cg.y)));
+                        const float ei = fmaf(Au[ub], ci, fmaf(Bu[ub], gi, slk[ub]));
+                        hit = hit && (v + ei >= tauf[ub]);
+                        lb = v - ei;
+                    }
+                    if (hit) {
+                        list_insert(L, lb);
+                        if (cnt[ub] < a.cap)
+                            a.cand[cand_at(w * UB + ub, lane, cnt[ub], a.cap)] =
+                                make_int2(__float_as_int(v), orig);
+                        cnt[ub] += 1;
                     }
                 }
-                tau[ub] = vmax(tau[ub], list_tau(lst[ub], hidx, k_is_km));
-                tauf[ub] = act[ub] ? tau[ub] : pinf;
             }
         }
-        if constexpr (!WALK) {
-            if (!a.prune) return true;
-        }
-        // Stop test after this tile (Section III-C): every unvisited item i has
-        // key <= ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is sorted,
-        // so the next entry's bound covers all of them.  The norm-pruned brute
-        // force is the same test with theta_b = pi (bound = ||i||), over the
-        // suffix maxima of its norm-ordered tiles.
+        tau[ub] = vmax(tau[ub], list_tau(L, hidx, k_is_km));
+        tauf[ub] = act[ub] ? tau[ub] : pinf;
+        list_store(ub, L);
+    };
+
+    // Stop test after tile b (Section III-C); returns false once every user
+    // of the wave has stopped.  Every unvisited item i has key <=
+    // ||u|| bound_j(i) + f 2^-53 ||u|| ||i||, and the list is sorted, so the
+    // next entry's bound covers all of them.  The norm-pruned brute force is
+    // the same test with theta_b = pi (bound = ||i||), over the suffix maxima
+    // of its norm-ordered tiles.
+    auto stop_after = [&](int b) __attribute__((always_inline)) -> bool {
+        if constexpr (MODE == kSweepBrute) return true;
         const int64_t pnext = (int64_t)(b + 1) * kTile;
         bool any = false;
         if (b + 1 >= (WALK ? a.shared_blocks : 1)) {
@@ -579,30 +606,78 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     };
 
     // ---- item sweep --------------------------------------------------------
-    // Operands are loaded two tiles ahead into alternating register sets; the
-    // loads are unconditional (tile index clamped to the last tile) so the
-    // loop body is straight-line code with exact wait counts.
+    // With four user blocks, products and tests are interleaved over the
+    // blocks: the products of block j of tile b go into one of two
+    // accumulator tiles while the test of the block before it (block j - 1,
+    // or the last block of tile b - 1) reads the other, so the matrix cores
+    // work while the vector unit tests.  Block j of tile b uses accumulator
+    // (b UB + j) mod 2.  With one or two blocks, whose product chains are long
+    // (float32: 25 dependent products per block at f = 50) or few, all
+    // products of a tile come first (independent chains interleave), then the
+    // tests, and another wave of the SIMD keeps the matrix cores busy.  Operands
+    // are loaded two tiles ahead into alternating register sets, issued as
+    // soon as the tile's last products have read them; the loads are
+    // unconditional (tile index clamped to the last tile), so the loop body is
+    // straight-line code apart from the tests' branches.
     int b_done = n_blk;           // tiles visited (the walk may stop early)
     if (n_blk > 0) {
         const int last = n_blk - 1;
-        Op oA[NCH], oB[NCH];
-        int itA = -1, itB = -1, scA = 127, scB = 127;
-        float2 bmA, bmB, cgA = make_float2(0.0f, 0.0f), cgB = make_float2(0.0f, 0.0f);
-        floatx16_t acc[UB];
-        load_tile(0, oA, itA, scA, bmA, cgA);
-        load_tile(n_blk > 1 ? 1 : 0, oB, itB, scB, bmB, cgB);
+        Op ops[2][NCH];
+        int itm[2] = {-1, -1}, scl[2] = {127, 127};
+        float2 bmx[2], cgx[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+        floatx16_t acc[2];
+        int itP = -1;                 // the previous tile's item, bound and norms
+        float2 bmP = make_float2(0.0f, 0.0f), cgP = make_float2(0.0f, 0.0f);
+        load_tile(0, ops[0], itm[0], scl[0], bmx[0], cgx[0]);
+        load_tile(n_blk > 1 ? 1 : 0, ops[1], itm[1], scl[1], bmx[1], cgx[1]);
+        // tile b from operand set T (= b mod 2); false: every user stopped
+        // after tile b - 1 (tile b's products are then unused)
+        auto sweep = [&](int b, auto tconst) __attribute__((always_inline)) -> bool {
+            constexpr int T = decltype(tconst)::value;
+            const int itC = itm[T], scC = scl[T];
+            const float2 bmC = bmx[T], cgC = cgx[T];
+            if constexpr (UB <= 2) {
+                // all products of the tile (independent chains, interleaved
+                // by the compiler), then the tests and the stop test
+#pragma unroll
+                for (int j = 0; j < UB; ++j) acc[j] = score_one(b, ops[T], scC, j);
+                load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
+#pragma unroll
+                for (int j = 0; j < UB; ++j) test_block(j, acc[j], itC, bmC, cgC);
+                return stop_after(b);
+            } else {
+#pragma unroll
+                for (int j = 0; j < UB; ++j) {
+                    acc[(T * UB + j) & 1] = score_one(b, ops[T], scC, j);
+                    if (j == UB - 1)
+                        load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
+                    if (j == 0) {
+                        if (b > 0) {
+                            test_block(UB - 1, acc[(T * UB + 1) & 1], itP, bmP, cgP);
+                            if (!stop_after(b - 1)) return false;
+                        }
+                    } else {
+                        test_block(j - 1, acc[(T * UB + j - 1) & 1], itC, bmC, cgC);
+                    }
+                }
+                itP = itC;
+                bmP = bmC;
+                cgP = cgC;
+                return true;
+            }
+        };
+        // a false sweep: every user stopped after tile b (two blocks or
+        // fewer) or after tile b - 1 (rotated blocks)
+        constexpr int kStopLag = UB <= 2 ? 1 : 0;
         for (int b = 0; b < n_blk; b += 2) {
-            score_tile(b, oA, scA, acc);
-            const int eA = itA;
-            const float2 mA = bmA, gA = cgA;
-            load_tile(b + 2 < last ? b + 2 : last, oA, itA, scA, bmA, cgA);
-            if (!epi_tile(b, acc, eA, mA, gA)) { b_done = b + 1; break; }
+            if (!sweep(b, std::integral_constant<int, 0>{})) { b_done = b + kStopLag; break; }
             if (b + 1 >= n_blk) break;
-            score_tile(b + 1, oB, scB, acc);
-            const int eB = itB;
-            const float2 mB = bmB, gB = cgB;
-            load_tile(b + 3 < last ? b + 3 : last, oB, itB, scB, bmB, cgB);
-            if (!epi_tile(b + 1, acc, eB, mB, gB)) { b_done = b + 2; break; }
+            if (!sweep(b + 1, std::integral_constant<int, 1>{})) { b_done = b + 1 + kStopLag; break; }
+        }
+        if (UB > 2 && b_done == n_blk) {
+            // the last block of the last tile (accumulator (last UB + UB - 1) mod 2)
+            if ((last & 1) == 0) test_block(UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
+            else test_block(UB - 1, acc[(2 * UB - 1) & 1], itP, bmP, cgP);
         }
     }
 
@@ -616,18 +691,22 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // tau_u.  Same rules as certify_kernel, without the round trip through
     // memory for the per-user state.
     if constexpr (fused_certify(PREC, KM, UB)) {
-        const int ubl = h;
-        const int x0 = xor32_i(cnt[0]);
-        const int x1 = xor32_i(cnt[UB - 1]);
-        const int cA = (ubl == 1) ? x1 : cnt[0];          // the list of lane n
-        const int cB = (ubl == 1) ? cnt[UB - 1] : x0;     // the list of lane n + 32
-        const float uA = (ubl == 1) ? Au[UB - 1] : Au[0];
-        const float uB = (ubl == 1) ? Bu[UB - 1] : Bu[0];
-        const float us = (ubl == 1) ? slk[UB - 1] : slk[0];
-        const float ut = (ubl == 1) ? tau[UB - 1] : tau[0];
-        const bool ud = (ubl == 1) ? dgn[UB - 1] : dgn[0];
+#pragma unroll
+      for (int ps = 0; ps < UB / 2; ++ps) {
+        // pass ps: lanes of half h certify the users of block 2 ps + h
+        const int b0 = 2 * ps, b1 = 2 * ps + 1;
+        const int ubl = b0 + h;
+        const int x0 = xor32_i(cnt[b0]);
+        const int x1 = xor32_i(cnt[b1]);
+        const int cA = (h == 1) ? x1 : cnt[b0];          // the list of lane n
+        const int cB = (h == 1) ? cnt[b1] : x0;          // the list of lane n + 32
+        const float ut = (h == 1) ? tau[b1] : tau[b0];
+        const bool ud = (h == 1) ? dgn[b1] : dgn[b0];
+        const float uA = (h == 1) ? Au[b1] : Au[b0];
+        const float uB = (h == 1) ? Bu[b1] : Bu[b0];
+        const float us = (h == 1) ? slk[b1] : slk[b0];
         bool valid = false;
-        const int64_t u = (h < UB) ? user_of(a, UB, w, ubl, n, tile, &valid) : 0;
+        const int64_t u = user_of(a, UB, w, ubl, n, tile, &valid);
         unsigned long long st_cand = 0, st_resc = 0, st_max = 0;
         double st_abs = 0.0, st_rel = 0.0;
         if (valid && !ud) {
@@ -635,8 +714,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             const int m0 = cA < cap ? cA : cap, m1 = cB < cap ? cB : cap;
             bool bad = (cA > cap) || (cB > cap);
             const int tot = m0 + m1;
-            const int2* list0 = a.cand + (((w * UB + ubl) << 6) + n) * (int64_t)cap;
-            const int2* list1 = a.cand + (((w * UB + ubl) << 6) + n + 32) * (int64_t)cap;
+            // the user's two lists (its lane n and lane n + 32 halves)
+            const int64_t base0 = cand_at(w * UB + ubl, n, 0, cap);
+            const int64_t base1 = cand_at(w * UB + ubl, n + 32, 0, cap);
             const float* urow = a.U + u * a.f;
             double tau64 = (double)ut;   // kept pairs: key >= tau64
             float thr = ut;              // rescored pairs: upper bound >= thr (<= tau64)
@@ -650,37 +730,45 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
             for (int q = 0; q < KM; ++q) { tk[q] = -__builtin_inf(); ti[q] = 0x7fffffff; }
             int nkeep = 0;
-            for (int j0 = 0; j0 < tot; j0 += 4) {
-                int2 e[4];
-                float Ci[4], Gi[4];
+            for (int j0 = 0; j0 < tot; j0 += 8) {
+                int2 e[8];
+                float Ci[8], Gi[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     const int j = j0 + q;
                     e[q] = make_int2(0, -1);
-                    if (j < tot) e[q] = (j < m0) ? list0[j] : list1[j - m0];
+                    if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j : base1 + (j - m0)];
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     const int item = e[q].y;
                     Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
                     Gi[q] = (item >= 0) ? a.Gorig[item] : 0.0f;
                 }
-                int it[4];
+                int it[8];
                 bool anyk = false;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     const float sv = __int_as_float(e[q].x);
                     const float eb = fmaf(uA, Ci[q], fmaf(uB, Gi[q], us));
                     it[q] = (e[q].y >= 0 && sv + eb >= thr) ? e[q].y : -1;
                     anyk = anyk || it[q] >= 0;
                 }
                 if (!anyk) continue;
-                double k4[4];
-                keys4(urow, a.I, a.f, it, k4);
+                double k8[8];
+                {
+                    // two groups of four rows (one memory latency per 32 FMAs)
+                    const int ia[4] = {it[0], it[1], it[2], it[3]}, ib[4] = {it[4], it[5], it[6], it[7]};
+                    double ka[4], kb[4];
+                    keys4(urow, a.I, a.f, ia, ka);
+                    keys4(urow, a.I, a.f, ib, kb);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < 4; ++q) { k8[q] = ka[q]; k8[q + 4] = kb[q]; }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
                     if (it[q] < 0) continue;
-                    const double key = k4[q];
+                    const double key = k8[q];
                     ++st_resc;
                     if (a.want_stats) {
                         const double err = fabs((double)__int_as_float(e[q].x) - key);
@@ -751,6 +839,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 atomic_max_nonneg((double*)&a.ctrl->max_rel_err, st_rel);
             }
         }
+      }
     }
 
     // ---- hand the per-user state to certification -------------------------
@@ -773,24 +862,34 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     }
 }
 
-template <int PREC, int KM, int NCH, int UB>
+template <int PREC, int KM, int NCH>
 static hipError_t go_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
-    if (a.walk)
-        screen_kernel<PREC, KM, NCH, UB, true><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
-    else
-        screen_kernel<PREC, KM, NCH, UB, false><<<dim3((unsigned)p.n_waves), dim3(64), 0, s>>>(a);
+    // blocks per wave: fewer where a stop test keeps waves until their
+    // slowest user stops
+    constexpr int UBS = ub_for(PREC, KM, NCH, true), UBB = ub_for(PREC, KM, NCH, false);
+    const dim3 grid((unsigned)p.n_waves), blk(64);
+    if (a.walk) {
+        if (p.UB != UBS) return hipErrorInvalidValue;   // plan and kernel disagree
+        screen_kernel<PREC, KM, NCH, UBS, kSweepWalk><<<grid, blk, 0, s>>>(a);
+    } else if (a.prune) {
+        if (p.UB != UBS) return hipErrorInvalidValue;
+        screen_kernel<PREC, KM, NCH, UBS, kSweepPruned><<<grid, blk, 0, s>>>(a);
+    } else {
+        if (p.UB != UBB) return hipErrorInvalidValue;
+        screen_kernel<PREC, KM, NCH, UBB, kSweepBrute><<<grid, blk, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
 template <int PREC, int NCH>
 static hipError_t screen_km(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s) {
     switch (p.KM) {
-        case 1:  return go_screen<PREC, 1, NCH, ub_for(PREC, 1, NCH)>(p, a, s);
-        case 8:  return go_screen<PREC, 8, NCH, ub_for(PREC, 8, NCH)>(p, a, s);
-        case 10: return go_screen<PREC, 10, NCH, ub_for(PREC, 10, NCH)>(p, a, s);
-        case 16: return go_screen<PREC, 16, NCH, ub_for(PREC, 16, NCH)>(p, a, s);
-        case 32: return go_screen<PREC, 32, NCH, ub_for(PREC, 32, NCH)>(p, a, s);
-        default: return go_screen<PREC, 64, NCH, ub_for(PREC, 64, NCH)>(p, a, s);
+        case 1:  return go_screen<PREC, 1, NCH>(p, a, s);
+        case 8:  return go_screen<PREC, 8, NCH>(p, a, s);
+        case 10: return go_screen<PREC, 10, NCH>(p, a, s);
+        case 16: return go_screen<PREC, 16, NCH>(p, a, s);
+        case 32: return go_screen<PREC, 32, NCH>(p, a, s);
+        default: return go_screen<PREC, 64, NCH>(p, a, s);
     }
 }
 
