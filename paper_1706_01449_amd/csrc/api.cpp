@@ -134,7 +134,7 @@ bool make_screen_plan(int64_t n_u, int64_t n_i, int f, int K, int prec, bool sto
 struct BmmLayout {
     size_t ctrl, ctrlb, hist, uflag, zero_end;
     size_t flist, uscal, bucket, perm, Corig, Gorig, Eorig, kexp, qrow, packed, pscale, blockmax,
-        tailmax;
+        tailmax, cgpos;
     size_t qrowb, Gorigb, Eorigb;   // bfloat16 rows of the E4M3 certification cascade
     size_t cnt, cand, fbkeys, total;
 };
@@ -166,6 +166,7 @@ static BmmLayout bmm_layout(const ScreenPlan& p) {
         L.packed = take((size_t)p.n_i_pad * p.f_pad * esz);
         L.pscale = take((size_t)p.n_i_pad * 4);
         L.blockmax = take((size_t)p.n_blk * 8);
+        L.cgpos = take((size_t)p.n_i_pad * 8);
         L.tailmax = take((size_t)p.n_blk * 4);
         if (casc) {
             L.qrowb = take((size_t)p.n_i * cascade_stride(p.f) * 2);
@@ -410,6 +411,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
             ia.packed = ws + L.packed;
             ia.pscale = (int*)(ws + L.pscale);
             ia.blockmax = (float2*)(ws + L.blockmax);
+            ia.cgpos = (float2*)(ws + L.cgpos);
             ia.ctrl = ctrl;
             if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
                 return hip_fail(e, "item preparation");
@@ -466,6 +468,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
         a.packed = ws + L.packed;
         a.pscale = (const int*)(ws + L.pscale);
         a.blockmax = (const float2*)(ws + L.blockmax);
+        a.cgpos = (const float2*)(ws + L.cgpos);
         a.tailmax = (const float*)(ws + L.tailmax);
         a.prune = prune;
         a.perm = (const int*)(ws + L.perm);

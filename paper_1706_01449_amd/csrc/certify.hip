@@ -73,6 +73,8 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
                 if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j : base1 + (j - m0)];
             }
 #pragma unroll
+            for (int q = 0; q < 4; ++q) e[q].y = cand_item(a, e[q].y);
+#pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int item = e[q].y;
                 Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
@@ -472,6 +474,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
         const int j = base + lane;
         int2 e = make_int2(0, -1);
         if (j < tot) e = a.cand[(j < c0) ? base0 + j : base1 + (j - c0)];
+        e.y = cand_item(a, e.y);
         bool keep = false;
         if (e.y >= 0) {
             const float eb = fmaf(us.x, a.Corig[e.y], fmaf(us.y, a.Gorig[e.y], us.z));

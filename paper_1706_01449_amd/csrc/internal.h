@@ -44,6 +44,7 @@ __host__ __device__ inline int64_t cand_at(int64_t blk, int lane, int j, int cap
 }
 inline size_t cand_bytes(int64_t n_ublk, int cap) { return (size_t)n_ublk * 64 * cap * 8; }
 
+
 // Device-resident control block of one call.  Zeroed at the start of every
 // call by a fill kernel (never by a memset node, so callers may capture the
 // call in a graph).
@@ -91,7 +92,8 @@ struct ScreenArgs {
     const void* packed;
     const int* pscale;        // FP8: E8M0 scale byte per sorted position
     const float2* blockmax;   // per item tile: (max C, max G)
-    const int* perm;          // sorted position -> item index
+    const int* perm;          // sorted position -> item index (-1 past the last item)
+    const float2* cgpos;      // (C_i, G_i) by sorted position
     const float* tailmax;     // per tile: max ||i|| over this and all later tiles
     int prune;                // norm pruning: a user stops once ||u|| tailmax < tau_u
     // Maximus walk
@@ -122,10 +124,17 @@ struct ScreenArgs {
     float4* uscal;            // n_u: (A_u, B_u, slack_u, tau_u)
     int64_t n_ublk;           // user blocks with candidate storage
     int* cnt;                 // n_ublk * 64 candidate counts
-    int2* cand;               // n_ublk * 64 lists of cap candidates (score bits, item index)
+    int2* cand;               // n_ublk * 64 lists of cap candidates (score bits, reference):
+                              // the reference is the item (walk) or the sorted position
+                              // (brute force), see cand_item
     int32_t* out_idx;
     double* out_score;
 };
+
+// Item index named by a candidate entry's reference (-1 stays -1).
+__device__ inline int cand_item(const ScreenArgs& a, int ref) {
+    return (a.walk || ref < 0) ? ref : a.perm[ref];
+}
 
 struct FallbackArgs {
     const float* U;
@@ -156,6 +165,7 @@ struct ItemPrepArgs {
     void* packed;
     int* pscale;
     float2* blockmax;
+    float2* cgpos;            // (C_i, G_i) by sorted position (nullable)
     Ctrl* ctrl;
 };
 

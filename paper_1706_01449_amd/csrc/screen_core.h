@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
                 ai[c] = P::load_packed(a.packed, b, c, NCH, lane);
-            item = a.perm[p];                       // -1 past the last item
+            item = 0;                               // hits name positions (no item needed)
             if (PREC == PREC_FP8) iscale = a.pscale[p];
         } else {
             item = clist[p];                        // -1 past the last item
@@ -519,7 +519,14 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // Streaming top-K over one user block of one tile: a wave-wide test of
     // the lanes' tile maxima against tau_u - e_tile(u); only when some lane
     // passes are the row groups and rows walked.
-    auto test_block = [&](int ub, const floatx16_t& sc, int item, float2 bm, float2 cg)
+    // A hit is appended as (score, reference): the walk names the item (its
+    // tile rows come from a list, gathered by item), the brute force names
+    // the sorted position b 32 + row, which needs no exchange between lanes;
+    // certification maps positions to items.  The store goes to slot
+    // min(count, cap - 1): a list that overflows sends its user to the exact
+    // path, whatever its last slot holds.
+    const int lane_slot0 = lane * a.cap;
+    auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 bm, float2 cg)
         __attribute__((always_inline)) {
         const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
         const float thr = tauf[ub] - ee;
@@ -539,13 +546,20 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float v = sc[4 * g + q];
-                bool hit = (v >= thr) && (v > ninf);
+                bool hit = v >= thr;
                 if (ballot(hit)) {
-                    // item index of output row 8g + 4h + q, held by lane (row);
-                    // -1 for rows past the last item
                     const int row = 8 * g + 4 * h + q;
-                    const int orig = __builtin_amdgcn_ds_bpermute(row << 2, item);
-                    hit = hit && orig >= 0;
+                    int ref;
+                    if constexpr (WALK) {
+                        // item index of output row 8g + 4h + q, held by lane
+                        // (row); -1 for rows past the end of the list
+                        ref = __builtin_amdgcn_ds_bpermute(row << 2, item);
+                        hit = hit && ref >= 0;
+                    } else {
+                        // rows past the last item hold zero operands (score 0)
+                        ref = b * kTile + row;
+                        hit = hit && (int64_t)ref < a.n_i;
+                    }
                     float lb = v - ee;
                     if constexpr (pair_bound_walk(WALK, PREC, KM, NCH)) {
                         // walk tiles mix item norms, so the tile's bound is
@@ -560,9 +574,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     }
                     if (hit) {
                         list_insert(L, lb);
-                        if (cnt[ub] < a.cap)
-                            a.cand[cand_at(w * UB + ub, lane, cnt[ub], a.cap)] =
-                                make_int2(__float_as_int(v), orig);
+                        int2* const cb = a.cand + cand_at(w * UB + ub, 0, 0, a.cap);
+                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1)] =
+                            make_int2(__float_as_int(v), ref);
                         cnt[ub] += 1;
                     }
                 }
@@ -650,7 +664,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 if constexpr (PREC == PREC_FP32) __builtin_amdgcn_sched_barrier(0);
                 load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
 #pragma unroll
-                for (int j = 0; j < UB; ++j) test_block(j, acc[j], itC, bmC, cgC);
+                for (int j = 0; j < UB; ++j) test_block(b, j, acc[j], itC, bmC, cgC);
                 return stop_after(b);
             } else {
 #pragma unroll
@@ -660,11 +674,11 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
                     if (j == 0) {
                         if (b > 0) {
-                            test_block(UB - 1, acc[(T * UB + 1) & 1], itP, bmP, cgP);
+                            test_block(b - 1, UB - 1, acc[(T * UB + 1) & 1], itP, bmP, cgP);
                             if (!stop_after(b - 1)) return false;
                         }
                     } else {
-                        test_block(j - 1, acc[(T * UB + j - 1) & 1], itC, bmC, cgC);
+                        test_block(b, j - 1, acc[(T * UB + j - 1) & 1], itC, bmC, cgC);
                     }
                 }
                 itP = itC;
@@ -683,8 +697,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         }
         if (UB > 2 && b_done == n_blk) {
             // the last block of the last tile (accumulator (last UB + UB - 1) mod 2)
-            if ((last & 1) == 0) test_block(UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
-            else test_block(UB - 1, acc[(2 * UB - 1) & 1], itP, bmP, cgP);
+            if ((last & 1) == 0) test_block(last, UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
+            else test_block(last, UB - 1, acc[(2 * UB - 1) & 1], itP, bmP, cgP);
         }
     }
 
@@ -748,9 +762,17 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const int item = e[q].y;
-                    Ci[q] = (item >= 0) ? a.Corig[item] : 0.0f;
-                    Gi[q] = (item >= 0) ? a.Gorig[item] : 0.0f;
+                    const int ref = e[q].y;
+                    if constexpr (WALK) {
+                        Ci[q] = (ref >= 0) ? a.Corig[ref] : 0.0f;
+                        Gi[q] = (ref >= 0) ? a.Gorig[ref] : 0.0f;
+                    } else {
+                        // sorted position: its norms and its item, read together
+                        const float2 cg = (ref >= 0) ? a.cgpos[ref] : make_float2(0.0f, 0.0f);
+                        Ci[q] = cg.x;
+                        Gi[q] = cg.y;
+                        e[q].y = (ref >= 0) ? a.perm[ref] : -1;
+                    }
                 }
                 int it[8];
                 bool anyk = false;
