@@ -475,12 +475,49 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         }
     };
 
-    // ---- warm-up: seed tau from per-slot maxima of the leading tiles -----
-    // Slot (s, r) keeps the max over tiles b = s (mod S) of this lane's row r:
-    // each slot max is the screened score of one distinct item, so the K-th
-    // largest of their lower bounds (over the user's two lanes) is a valid
-    // lower bound on the user's K-th largest key.  The leading tiles hold the
-    // largest-norm items (brute force) or the best-bound items (walk).
+    // ---- warm-up -------------------------------------------------------------
+    // Brute force: the lower bounds of every item of the W leading tiles (the
+    // largest norms) go into the K-lists, tile by tile for all blocks, so tau
+    // starts at the K-th largest lower bound over those items; the main sweep
+    // covers tiles W and later, and the leading tiles are scored once more at
+    // the end, with the final tau, to record their candidates (with no list
+    // update).  Hits, which cost far more than a tile test, are thereby mostly
+    // the user's final candidates.
+    constexpr bool DENSE_WARM = MODE == kSweepBrute;
+    const int W = DENSE_WARM ? (a.warm_rounds * S < n_blk ? a.warm_rounds * S : n_blk) : 0;
+    if constexpr (DENSE_WARM) {
+        float L[UB][KM];
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub) list_reset(L[ub], a.K);
+        for (int b = 0; b < W; ++b) {
+            Op ai[NCH];
+            int it = -1, sc = 127;
+            float2 bmw;
+            float2 cgw;
+            load_tile(b, ai, it, sc, bmw, cgw);
+#pragma unroll
+            for (int ub = 0; ub < UB; ++ub) {
+                floatx16_t acc = score_one(b, ai, sc, ub);
+                mask_rows(b, acc);
+                const float ee = fmaf(Au[ub], bmw.x, fmaf(Bu[ub], bmw.y, slk[ub]));
+#pragma unroll
+                for (int r = 0; r < 16; ++r) list_insert(L[ub], acc[r] - ee);
+            }
+        }
+#pragma unroll
+        for (int ub = 0; ub < UB; ++ub) {
+            tau[ub] = list_tau(L[ub], hidx, k_is_km);
+            list_store(ub, L[ub]);
+            tauf[ub] = act[ub] ? tau[ub] : pinf;
+        }
+    } else {
+    // Walk and norm-pruned sweep: tau from per-slot maxima of the leading
+    // tiles.  Slot (s, r) keeps the max over tiles b = s (mod S) of this
+    // lane's row r: each slot max is the screened score of one distinct item,
+    // so the K-th largest of their lower bounds (over the user's two lanes)
+    // is a valid lower bound on the user's K-th largest key.  The leading
+    // tiles hold the largest-norm items (norm-pruned) or the best-bound items
+    // (walk).
     // One user block at a time, so that only one block's slot maxima are live.
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
@@ -514,6 +551,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         list_reset(L, a.K);
         list_store(ub, L);
         tauf[ub] = act[ub] ? tau[ub] : pinf;
+    }
     }
 
     // Streaming top-K over one user block of one tile: a wave-wide test of
@@ -634,7 +672,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // unconditional (tile index clamped to the last tile), so the loop body is
     // straight-line code apart from the tests' branches.
     int b_done = n_blk;           // tiles visited (the walk may stop early)
-    if (n_blk > 0) {
+    const int b0 = W;             // first tile of the main sweep
+    if (n_blk > b0) {
         const int last = n_blk - 1;
         Op ops[2][NCH];
         int itm[2] = {-1, -1}, scl[2] = {127, 127};
@@ -642,8 +681,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         floatx16_t acc[2];
         int itP = -1;                 // the previous tile's item, bound and norms
         float2 bmP = make_float2(0.0f, 0.0f), cgP = make_float2(0.0f, 0.0f);
-        load_tile(0, ops[0], itm[0], scl[0], bmx[0], cgx[0]);
-        load_tile(n_blk > 1 ? 1 : 0, ops[1], itm[1], scl[1], bmx[1], cgx[1]);
+        load_tile(b0, ops[0], itm[0], scl[0], bmx[0], cgx[0]);
+        load_tile(b0 + 1 < n_blk ? b0 + 1 : b0, ops[1], itm[1], scl[1], bmx[1], cgx[1]);
         // tile b from operand set T (= b mod 2); false: every user stopped
         // after tile b - 1 (tile b's products are then unused)
         auto sweep = [&](int b, auto tconst) __attribute__((always_inline)) -> bool {
@@ -673,7 +712,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     if (j == UB - 1)
                         load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
                     if (j == 0) {
-                        if (b > 0) {
+                        if (b > b0) {
                             test_block(b - 1, UB - 1, acc[(T * UB + 1) & 1], itP, bmP, cgP);
                             if (!stop_after(b - 1)) return false;
                         }
@@ -690,15 +729,46 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         // a false sweep: every user stopped after tile b (two blocks or
         // fewer) or after tile b - 1 (rotated blocks)
         constexpr int kStopLag = UB <= 2 ? 1 : 0;
-        for (int b = 0; b < n_blk; b += 2) {
+        for (int b = b0; b < n_blk; b += 2) {
             if (!sweep(b, std::integral_constant<int, 0>{})) { b_done = b + kStopLag; break; }
             if (b + 1 >= n_blk) break;
             if (!sweep(b + 1, std::integral_constant<int, 1>{})) { b_done = b + 1 + kStopLag; break; }
         }
         if (UB > 2 && b_done == n_blk) {
-            // the last block of the last tile (accumulator (last UB + UB - 1) mod 2)
-            if ((last & 1) == 0) test_block(last, UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
+            // the last block of the last tile (accumulator ((last - b0) UB + UB - 1) mod 2)
+            if (((last - b0) & 1) == 0) test_block(last, UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
             else test_block(last, UB - 1, acc[(2 * UB - 1) & 1], itP, bmP, cgP);
+        }
+    }
+
+    // ---- brute force: candidates of the leading tiles, final tau ------------
+    if constexpr (DENSE_WARM) {
+        for (int b = 0; b < W; ++b) {
+            Op ai[NCH];
+            int it = -1, sc = 127;
+            float2 bm;
+            float2 cgw;
+            load_tile(b, ai, it, sc, bm, cgw);
+            const int rem = (int)(a.n_i - (int64_t)b * kTile);   // rows holding items
+#pragma unroll
+            for (int ub = 0; ub < UB; ++ub) {
+                const floatx16_t v = score_one(b, ai, sc, ub);
+                const float thr = tauf[ub] - fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
+                float m = vmax(v[0], v[1]);
+#pragma unroll
+                for (int r = 2; r < 16; r += 2) m = vmax(m, vmax(v[r], v[r + 1]));
+                if (!ballot(m >= thr)) continue;
+                int2* const cb = a.cand + cand_at(w * UB + ub, 0, 0, a.cap);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (v[r] >= thr && row < rem) {
+                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1)] =
+                            make_int2(__float_as_int(v[r]), b * kTile + row);
+                        cnt[ub] += 1;
+                    }
+                }
+            }
         }
     }
 
