@@ -299,6 +299,33 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
     return out
 
 
+def maximus_build_only(Cs, steps, warmup):
+    """Maximus builds alone (480,000 x 17,770 clustered, f = 50, 3 k-means
+    updates): median and min of per-build wall times, the index freed between
+    builds."""
+    import torch
+    import mipsgen
+    import paper_1706_01449_amd as mips
+    U, I = mipsgen.generate("clustered", 0)
+    Ut = torch.from_numpy(U).cuda()
+    It = torch.from_numpy(I).cuda()
+    torch.cuda.synchronize()
+    for C in Cs:
+        ts = []
+        for rep in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ix = mips.maximus_build(Ut, It, C, 3, 0, 0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            del ix
+            if rep >= warmup:
+                ts.append((t1 - t0) * 1e3)
+        ts.sort()
+        print(json.dumps({"maximus_build_C": C, "build_ms_median": ts[len(ts) // 2],
+                          "build_ms_min": ts[0], "builds": len(ts)}), flush=True)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -351,6 +378,9 @@ def main():
                     help="skip the Maximus / precision-form / backward measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--maximus-build", default="", metavar="C,C,...",
+                    help="only time Maximus index builds on the clustered workload at these "
+                         "cluster counts (one JSON line each) and exit")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the screen kernel sources and exit")
     args = ap.parse_args()
@@ -359,6 +389,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.maximus_build:
+        maximus_build_only([int(c) for c in args.maximus_build.split(",")], args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "

@@ -177,6 +177,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_scan4096(unsigned int* hist, hipStream_t s);
 hipError_t launch_tailmax(const float2* blockmax, int64_t n_blk, float* tailmax, hipStream_t s);
 hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStream_t s);
+// norms and screen copies of the same items for up to three precisions in
+// one pass (a[p] null: precision p skipped)
+hipError_t launch_item_stats3(const ItemPrepArgs* const (&a)[3], hipStream_t s);
 hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_fp32(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_bf16(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);

@@ -22,12 +22,45 @@ namespace mips {
 // ---------------------------------------------------------------------------
 // Small helpers.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) absmax_kernel(const float* X, int64_t n, unsigned int* out) {
+// dst = src (n floats) and max |x| over them (atomic max of the float bits);
+// dst is 16-byte aligned, src float4 loads when it is too.  Four loads in
+// flight per thread.
+__global__ void __launch_bounds__(256) copy_absmax_kernel(const float* __restrict__ src,
+                                                          float* __restrict__ dst, int64_t n,
+                                                          unsigned int* out) {
     __shared__ float wm[4];
     float m = 0.0f;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(X[i]));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if ((((uintptr_t)src) & 15) == 0) {
+        const int64_t n4 = n >> 2;
+        const float4* s4 = (const float4*)src;
+        float4* d4 = (float4*)dst;
+        for (int64_t i = t0; i < n4; i += 4 * stride) {
+            float4 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (i + r * stride < n4) v[r] = s4[i + r * stride];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (i + r * stride < n4) {
+                    d4[i + r * stride] = v[r];
+                    m = fmaxf(m, fmaxf(fmaxf(fabsf(v[r].x), fabsf(v[r].y)),
+                                       fmaxf(fabsf(v[r].z), fabsf(v[r].w))));
+                }
+            }
+        }
+        for (int64_t k = (n4 << 2) + t0; k < n; k += stride) {
+            dst[k] = src[k];
+            m = fmaxf(m, fabsf(src[k]));
+        }
+    } else {
+        for (int64_t k = t0; k < n; k += stride) {
+            const float x = src[k];
+            dst[k] = x;
+            m = fmaxf(m, fabsf(x));
+        }
+    }
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -43,170 +76,355 @@ __device__ __forceinline__ double fixed_scale(int64_t n, unsigned int absmax_bit
     return ldexp(1.0, e);
 }
 
-__global__ void gather_rows_kernel(const float* U, int f, const int* idx, int C, double* cent) {
+// splitmix64 (Steele, Lea and Flood 2014): output k of the stream seeded by s.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t s, uint64_t k) {
+    uint64_t z = s + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Initial centroids: the user order cut into C strata [c n_u / C, (c+1) n_u / C)
+// (each non-empty as C <= n_u), one user drawn uniformly from each, so the
+// C users are distinct.
+__global__ void forgy_kernel(const float* __restrict__ U, int64_t n_u, int f, int C, uint64_t seed,
+                             double* cent) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)C * f) return;
     const int c = (int)(t / f), j = (int)(t - (int64_t)c * f);
-    cent[t] = (double)U[(int64_t)idx[c] * f + j];
+    const int64_t lo = (int64_t)c * n_u / C, hi = (int64_t)(c + 1) * n_u / C;
+    const uint64_t r = splitmix64_at(seed ^ 0x6A09E667F3BCC909ull, (uint64_t)c);
+    const int64_t pick = lo + (int64_t)(r % (uint64_t)(hi - lo));
+    cent[t] = (double)U[pick * f + j];
 }
 
-__global__ void cent_prep_kernel(const double* cent, int C, int f, float* cent32, float* cnorm2) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    float s = 0.0f;
-    for (int j = 0; j < f; ++j) {
-        const float x = (float)cent[(int64_t)c * f + j];
-        cent32[(int64_t)c * f + j] = x;
-        s = fmaf(x, x, s);
-    }
-    cnorm2[c] = s;
+// ---------------------------------------------------------------------------
+// Nearest centroid on the matrix cores.  Centroid c is extended to
+// [c, ||c||^2, 0, ...] and user u to [u, -1/2, 0, ...] (length 2 ks), so the
+// float32 product is u.c - ||c||^2 / 2, whose largest value over c marks the
+// nearest centroid in Euclidean distance (||u||^2 is common to all c).  Ties
+// go to the lower centroid index.
+//
+// 32x32x2 float32 MFMA tiles: centroids are rows (operand A), users columns
+// (operand B); lane l holds user l%32 and the 16 centroids
+// {8g + 4(l/32) + q} of the tile; lane half h = l/32 owns the extended
+// coordinates [h ks, (h+1) ks).  The centroid operand is kept in a
+// lane-ordered image (per tile: ks/2 pairs x 64 lanes x 2 floats, written
+// by cent_prep_kernel) that a workgroup copies into LDS as it is.
+// ---------------------------------------------------------------------------
+struct AssignArgs {
+    const float* U;
+    int64_t n_u;
+    int f, ks, C, ntile, chunk_tiles;
+    int stage;                 // users staged through LDS (f <= 64)
+    int lds_theta;             // final pass: per-workgroup theta maxima in LDS
+    const float* img;          // ntile * ks * 64 floats
+    int* assign;
+    // final pass (index build): theta_b of every cluster from its members
+    const double* chat;        // unit centroids, C x f (zero rows for zero centroids)
+    const double* cnorm;       // ||c|| in float64
+    unsigned long long* theta_bits;
+};
+
+constexpr int kAssignWaves = 4;
+constexpr int kAssignLds = 65536;      // dynamic LDS budget of the assignment kernel
+
+__host__ __device__ inline int assign_ks(int f) { return 2 * ((f + 4) / 4); }   // even, 2 ks >= f + 1
+inline size_t assign_theta_bytes(int C, bool final_pass) {
+    return (final_pass && C <= 1024) ? (((size_t)C * 8 + 15) & ~(size_t)15) : 0;
+}
+inline size_t assign_stage_bytes(int f) { return f <= 64 ? (size_t)kAssignWaves * 32 * f * 4 : 0; }
+inline int assign_chunk_tiles(int f, int C, bool final_pass) {
+    const int ks = assign_ks(f), ntile = (C + 31) / 32;
+    const size_t room = kAssignLds - assign_theta_bytes(C, final_pass) - assign_stage_bytes(f);
+    const int fit = (int)(room / ((size_t)ks * 256));
+    return std::max(1, std::min(ntile, fit));
 }
 
-// Nearest centroid by Euclidean distance ||u||^2 - 2 u.c + ||c||^2 (the
-// ||u||^2 term is common); ties go to the lower centroid index.  One thread
-// per user; centroids staged through LDS 64 at a time, factors 32 at a time.
-__global__ void __launch_bounds__(256) assign_kernel(const float* __restrict__ U, int64_t n_u,
-                                                     int f, const float* __restrict__ cent32,
-                                                     const float* __restrict__ cnorm2, int C,
-                                                     int* __restrict__ assign) {
-    extern __shared__ float sc[];                 // [64][f]
-    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool on = u < n_u;
-    const float* urow = U + (on ? u : 0) * f;
-    float best = __builtin_inff();
-    int bi = 0;
-    for (int c0 = 0; c0 < C; c0 += 64) {
-        const int nc = min(64, C - c0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < nc * f; t += blockDim.x) sc[t] = cent32[(int64_t)c0 * f + t];
-        __syncthreads();
-        float part[64];
+template <int KS, bool FINAL>
+__global__ void __launch_bounds__(256) assign_mfma_kernel(AssignArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    const int f = a.f, ks = a.ks, ksp = ks >> 1;
+    const size_t lt_bytes = FINAL && a.lds_theta ? (((size_t)a.C * 8 + 15) & ~(size_t)15) : 0;
+    unsigned long long* lt = (unsigned long long*)lds;
+    float* simg = (float*)(lds + lt_bytes);
+    float* sus = simg + (size_t)a.chunk_tiles * ks * 64 + (size_t)wave * 32 * f;   // this wave's users
+    const int nchunk = (a.ntile + a.chunk_tiles - 1) / a.chunk_tiles;
+    const int64_t n_ublk = (a.n_u + 31) >> 5;
+
+    auto stage_img = [&](int ch) {
+        const int t0 = ch * a.chunk_tiles, nt = min(a.chunk_tiles, a.ntile - t0);
+        const float4* src = (const float4*)(a.img + (size_t)t0 * ks * 64);
+        float4* dst = (float4*)simg;
+        const int n4 = nt * ks * 16;
+        for (int e = threadIdx.x; e < n4; e += blockDim.x) dst[e] = src[e];
+    };
+    if (FINAL && a.lds_theta)
+        for (int c = threadIdx.x; c < a.C; c += blockDim.x) lt[c] = 0ull;
+    if (nchunk == 1) stage_img(0);
+    __syncthreads();
+
+    for (int64_t base = (int64_t)blockIdx.x * kAssignWaves; base < n_ublk;
+         base += (int64_t)gridDim.x * kAssignWaves) {
+        const int64_t blk = base + wave;
+        const int64_t u0 = blk * 32;
+        const int nrows = blk < n_ublk ? (int)min((int64_t)32, a.n_u - u0) : 0;
+        const bool valid = n < nrows;
+        const float* urow = a.U + (valid ? u0 + n : 0) * f;
+        if (a.stage) {
+            // coalesced copy of the block's rows (contiguous) into this
+            // wave's LDS rows; LDS accesses of one wave complete in order
+            const float* src = a.U + (nrows ? u0 : 0) * f;
+            const int tot = nrows * f;
+#pragma unroll 4
+            for (int e = lane; e < tot; e += 64) sus[e] = src[e];
+        }
+        auto uval = [&](int j) -> float { return a.stage ? sus[n * f + j] : urow[j]; };
+        float ub[KS];
 #pragma unroll
-        for (int q = 0; q < 64; ++q) part[q] = 0.0f;
-        for (int j0 = 0; j0 < f; j0 += 32) {
-            float x[32];
+        for (int k = 0; k < KS; ++k) {
+            const int j = h * ks + k;
+            float v = 0.0f;
+            if (k < ks) v = (j < f) ? (valid ? uval(j) : 0.0f) : (j == f ? -0.5f : 0.0f);
+            ub[k] = v;
+        }
+        float bestv = -__builtin_inff();
+        int besti = 0;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            if (nchunk > 1) {
+                __syncthreads();
+                stage_img(ch);
+                __syncthreads();
+            }
+            const int t0 = ch * a.chunk_tiles, nt = min(a.chunk_tiles, a.ntile - t0);
+            for (int tl = 0; tl < nt; ++tl) {
+                floatx16_t acc;
 #pragma unroll
-            for (int q = 0; q < 32; ++q) x[q] = (j0 + q < f) ? urow[j0 + q] : 0.0f;
+                for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+                const float2* ip = (const float2*)simg + (size_t)tl * ksp * 64 + lane;
 #pragma unroll
-            for (int c = 0; c < 64; ++c) {
-                if (c < nc) {
-                    float acc = part[c];
+                for (int kp = 0; kp < KS / 2; ++kp) {
+                    if (kp < ksp) {
+                        const float2 av = ip[kp * 64];
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, ub[2 * kp], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, ub[2 * kp + 1], acc, 0, 0, 0);
+                    }
+                }
+                const int cb = (t0 + tl) * 32 + 4 * h;
 #pragma unroll
-                    for (int q = 0; q < 32; ++q)
-                        if (j0 + q < f) acc = fmaf(x[q], sc[c * f + j0 + q], acc);
-                    part[c] = acc;
+                for (int r = 0; r < 16; ++r) {
+                    const int c = cb + 8 * (r >> 2) + (r & 3);
+                    if (c < a.C && acc[r] > bestv) { bestv = acc[r]; besti = c; }
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < 64; ++c) {
-            if (c < nc) {
-                const float d = fmaf(-2.0f, part[c], cnorm2[c0 + c]);
-                if (d < best) { best = d; bi = c0 + c; }
+        {   // the user's two lanes hold disjoint centroid sets
+            const float ov = xor32_f(bestv);
+            const int oi = xor32_i(besti);
+            if (ov > bestv || (ov == bestv && oi < besti)) { bestv = ov; besti = oi; }
+        }
+        if (h == 0 && valid) a.assign[u0 + n] = besti;
+        if constexpr (FINAL) {
+            // angle between the user and its centroid in float64 (Kahan:
+            // 2 atan2(|u^ - c^|, |u^ + c^|)); lane half h sums the
+            // coordinates j with (j / 2) % 2 == h, so the two halves read
+            // neighbouring pairs of the unit centroid
+            double n2 = 0.0;
+            for (int j = 2 * h; j < f; j += 4) {
+                const double x0 = valid ? (double)uval(j) : 0.0;
+                n2 = fma(x0, x0, n2);
+                if (j + 1 < f) {
+                    const double x1 = valid ? (double)uval(j + 1) : 0.0;
+                    n2 = fma(x1, x1, n2);
+                }
+            }
+            n2 += xor32_d(n2);
+            const double nc = a.cnorm[besti];
+            const bool use = valid && n2 > 0.0 && nc > 0.0;
+            double d = 0.0, s = 0.0;
+            if (use) {
+                const double rinv = 1.0 / sqrt(n2);
+                const double* y = a.chat + (int64_t)besti * f;
+                for (int j = 2 * h; j < f; j += 4) {
+                    double y0, y1 = 0.0;
+                    if ((f & 1) == 0) {          // 16-byte aligned pair
+                        const double2 yy = *(const double2*)(y + j);
+                        y0 = yy.x;
+                        y1 = yy.y;
+                    } else {
+                        y0 = y[j];
+                        if (j + 1 < f) y1 = y[j + 1];
+                    }
+                    const double x0 = (double)uval(j) * rinv;
+                    const double p0 = x0 - y0, q0 = x0 + y0;
+                    d = fma(p0, p0, d);
+                    s = fma(q0, q0, s);
+                    if (j + 1 < f) {
+                        const double x1 = (double)uval(j + 1) * rinv;
+                        const double p1 = x1 - y1, q1 = x1 + y1;
+                        d = fma(p1, p1, d);
+                        s = fma(q1, q1, s);
+                    }
+                }
+            }
+            d += xor32_d(d);
+            s += xor32_d(s);
+            if (use && h == 0) {
+                const double th = 2.0 * atan2(sqrt(d), sqrt(s));
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(th);
+                if (a.lds_theta) atomicMax(&lt[besti], bits);
+                else atomicMax(&a.theta_bits[besti], bits);
             }
         }
     }
-    if (on) assign[u] = bi;
+    if (FINAL && a.lds_theta) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < a.C; c += blockDim.x)
+            if (lt[c]) atomicMax(&a.theta_bits[c], lt[c]);
+    }
 }
 
-// Fixed-point per-cluster sums and counts (order independent).  When the
-// C x f sums fit in LDS a workgroup first aggregates its 256 users there, so
-// each (cluster, factor) receives one global atomic per workgroup.
-__global__ void __launch_bounds__(256) kmeans_sum_kernel(const float* __restrict__ U, int64_t n_u,
-                                                         int f, const int* __restrict__ assign,
+// Per 32-centroid tile (rows staged through LDS): float32 squared norms,
+// float64 norms, unit centroids and the lane-ordered image of the extended
+// centroids; also clears the cluster counts for the next update.
+__global__ void __launch_bounds__(256) cent_prep_kernel(const double* __restrict__ cent, int C, int f,
+                                                        int ks, float* img, double* cnorm,
+                                                        double* chat, unsigned int* counts) {
+    extern __shared__ double srows[];          // 32 x f
+    __shared__ float n2s[32];
+    __shared__ double nrm[32];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int nr = min(32, C - t * 32);
+    const double* src = cent + (int64_t)t * 32 * f;
+    // rows through LDS unless they would not fit beside the static arrays
+    const bool stage = f <= 254;
+    if (stage)
+        for (int e = tid; e < nr * f; e += blockDim.x) srows[e] = src[e];
+    const double* rows = stage ? (const double*)srows : src;
+    __syncthreads();
+    if (tid < 32) {
+        const int c = t * 32 + tid;
+        float s = 0.0f;
+        double s64 = 0.0;
+        if (tid < nr) {
+            for (int j = 0; j < f; ++j) {
+                const double x = rows[tid * f + j];
+                const float xf = (float)x;
+                s = fmaf(xf, xf, s);
+                s64 += x * x;
+            }
+            cnorm[c] = sqrt(s64);
+            if (counts) counts[c] = 0u;
+        }
+        n2s[tid] = s;
+        nrm[tid] = sqrt(s64);
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * f; e += blockDim.x) {
+        const int r = e / f;
+        const double nc = nrm[r];
+        chat[(int64_t)t * 32 * f + e] = nc > 0.0 ? rows[e] * (1.0 / nc) : 0.0;
+    }
+    float* im = img + (size_t)t * ks * 64;
+    for (int e = tid; e < ks * 64; e += blockDim.x) {
+        const int kp = e >> 7, ln = (e >> 1) & 63, ee = e & 1;
+        const int r = ln & 31, j = (ln >> 5) * ks + 2 * kp + ee;
+        float v = 0.0f;
+        if (r < nr) v = j < f ? (float)rows[r * f + j] : (j == f ? n2s[r] : 0.0f);
+        im[e] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k-means update.  Fixed-point per-cluster sums (int64 adds are order
+// independent): workgroup (x, y) takes users [x R, (x+1) R) and clusters
+// [y cs, (y+1) cs).  The rows' floats are read four at a time, four such
+// loads in flight per thread, against the workgroup's assignments copied to
+// LDS; the sums gather in LDS and each non-zero (cluster, factor) sum is
+// added to the global one.
+// ---------------------------------------------------------------------------
+constexpr int kSumMaxRows = 2048;      // R <= kSumMaxRows (assignments in LDS)
+
+__global__ void __launch_bounds__(256) kmeans_sum_kernel(const float* __restrict__ U, int64_t n_u, int f,
+                                                         const int* __restrict__ assign,
                                                          const unsigned int* absmax_bits,
+                                                         int64_t rows_per_wg, int cs,
                                                          unsigned long long* sums,
                                                          unsigned int* counts, int C) {
-    __shared__ unsigned long long ls[4096];
-    __shared__ unsigned int lc[512];
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int c0 = blockIdx.y * cs, ncs = min(cs, C - c0);
+    if (ncs <= 0) return;                                         // whole workgroup
+    unsigned long long* ls = (unsigned long long*)lds;            // [cs][f]
+    unsigned int* lc = (unsigned int*)(ls + (size_t)cs * f);      // [cs]
+    int* la = (int*)(lc + cs);                                    // [R] cluster - c0
+    const int64_t lo = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t hi = min(n_u, lo + rows_per_wg);
+    const int nrow = (int)max((int64_t)0, hi - lo);
+    for (int t = threadIdx.x; t < ncs * f; t += blockDim.x) ls[t] = 0ull;
+    for (int t = threadIdx.x; t < ncs; t += blockDim.x) lc[t] = 0u;
+    for (int t = threadIdx.x; t < nrow; t += blockDim.x) la[t] = assign[lo + t] - c0;
+    __syncthreads();
     const double scale = fixed_scale(n_u, *absmax_bits);
-    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool local = (int64_t)C * f <= 4096 && C <= 512;
-    if (local) {
-        for (int t = threadIdx.x; t < C * f; t += blockDim.x) ls[t] = 0ull;
-        for (int t = threadIdx.x; t < C; t += blockDim.x) lc[t] = 0u;
-        __syncthreads();
-    }
-    if (u < n_u) {
-        const int c = assign[u];
-        const float* row = U + u * f;
-        if (local) {
-            atomicAdd(&lc[c], 1u);
-            for (int j = 0; j < f; ++j)
-                atomicAdd(&ls[c * f + j], (unsigned long long)llrint((double)row[j] * scale));
-        } else {
-            atomicAdd(&counts[c], 1u);
-            for (int j = 0; j < f; ++j)
-                atomicAdd(&sums[(int64_t)c * f + j], (unsigned long long)llrint((double)row[j] * scale));
+    // rows_per_wg is a multiple of 4 and U 16-byte aligned: float4 groups
+    const int nel = nrow * f, ng = (nel + 3) >> 2;
+    const float4* U4 = (const float4*)(U + lo * f);
+    for (int g0 = threadIdx.x; g0 < ng; g0 += 4 * 256) {
+        float4 v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int g = g0 + 256 * r;
+            if (4 * g + 4 <= nel) {
+                v[r] = U4[g];
+            } else if (g < ng) {
+                const float* p = U + lo * f + 4 * g;
+                v[r].x = p[0];
+                v[r].y = 4 * g + 1 < nel ? p[1] : 0.0f;
+                v[r].z = 4 * g + 2 < nel ? p[2] : 0.0f;
+                v[r].w = 4 * g + 3 < nel ? p[3] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int g = g0 + 256 * r;
+            if (g >= ng) continue;
+            const float x[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+            int row = (4 * g) / f;
+            int j = 4 * g - row * f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (4 * g + q < nel) {
+                    const int c = la[row];
+                    if ((unsigned)c < (unsigned)ncs) {
+                        atomicAdd(&ls[c * f + j], (unsigned long long)llrint((double)x[q] * scale));
+                        if (j == 0) atomicAdd(&lc[c], 1u);
+                    }
+                }
+                if (++j == f) { j = 0; ++row; }
+            }
         }
     }
-    if (local) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < C * f; t += blockDim.x)
-            if (ls[t]) atomicAdd(&sums[t], ls[t]);
-        for (int t = threadIdx.x; t < C; t += blockDim.x)
-            if (lc[t]) atomicAdd(&counts[t], lc[t]);
-    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ncs * f; t += blockDim.x)
+        if (ls[t]) atomicAdd(&sums[(int64_t)c0 * f + t], ls[t]);
+    for (int t = threadIdx.x; t < ncs; t += blockDim.x)
+        if (lc[t]) atomicAdd(&counts[c0 + t], lc[t]);
 }
 
-__global__ void kmeans_update_kernel(double* cent, int C, int f, const unsigned long long* sums,
+// New centroids from the sums (an empty cluster keeps its centroid); clears
+// the sums for the next update.
+__global__ void kmeans_update_kernel(double* cent, int C, int f, unsigned long long* sums,
                                      const unsigned int* counts, const unsigned int* absmax_bits,
                                      int64_t n_u) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)C * f) return;
     const int c = (int)(t / f);
     const unsigned int n = counts[c];
-    if (n == 0) return;   // an empty cluster keeps its centroid
+    const unsigned long long v = sums[t];
+    sums[t] = 0ull;
+    if (n == 0) return;
     const double scale = fixed_scale(n_u, *absmax_bits);
-    cent[t] = (double)(long long)sums[t] / scale / (double)n;
-}
-
-// Kahan's stable angle between a and b (float64): 2 atan2(|a^ - b^|, |a^ + b^|).
-__device__ __forceinline__ double stable_angle(const float* a, const double* b, int f, double na,
-                                               double nb) {
-    double d = 0.0, s = 0.0;
-    for (int j = 0; j < f; ++j) {
-        const double x = (double)a[j] / na, y = b[j] / nb;
-        d += (x - y) * (x - y);
-        s += (x + y) * (x + y);
-    }
-    return 2.0 * atan2(sqrt(d), sqrt(s));
-}
-
-// theta_b[c] = max over users of cluster c of the user-centroid angle (zero
-// users left out).  Non-negative doubles order like their bit patterns.
-// Workgroups stride over many users and keep the per-cluster maxima in LDS,
-// then merge them with one atomic per cluster and workgroup.
-__global__ void __launch_bounds__(256) theta_kernel(const float* __restrict__ U, int64_t n_u, int f,
-                                                    const int* __restrict__ assign,
-                                                    const double* __restrict__ cent,
-                                                    const double* __restrict__ cnorm, int C,
-                                                    unsigned long long* theta_bits) {
-    __shared__ unsigned long long lt[4096];
-    for (int c = threadIdx.x; c < C; c += blockDim.x) lt[c] = 0ull;
-    __syncthreads();
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_u;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const float* row = U + u * f;
-        double n2 = 0.0;
-        for (int j = 0; j < f; ++j) n2 += (double)row[j] * (double)row[j];
-        const int c = assign[u];
-        const double nc = cnorm[c];
-        if (!(n2 > 0.0) || !(nc > 0.0)) continue;
-        const double th = stable_angle(row, cent + (int64_t)c * f, f, sqrt(n2), nc);
-        atomicMax(&lt[c], (unsigned long long)__double_as_longlong(th));
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < C; c += blockDim.x)
-        if (lt[c]) atomicMax(&theta_bits[c], lt[c]);
-}
-
-__global__ void cnorm_kernel(const double* cent, int C, int f, double* cnorm) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    double s = 0.0;
-    for (int j = 0; j < f; ++j) s += cent[(int64_t)c * f + j] * cent[(int64_t)c * f + j];
-    cnorm[c] = sqrt(s);
+    cent[t] = (double)(long long)v / scale / (double)n;
 }
 
 // A zero centroid bounds nothing by angle: theta_b = pi (bound = ||i||).
@@ -229,68 +447,192 @@ __device__ __forceinline__ float key_to_float(uint32_t k) {
     return __uint_as_float(b);
 }
 
+// ---------------------------------------------------------------------------
 // Bound of Eq. (appx_bound) for every (cluster, item) in float64:
-// ||i|| cos(max(theta_ic - theta_b, 0)), widened by 2^-40 ||i|| for the
-// float64 evaluation of the angles and rounded up to float32.
-__global__ void bound_kernel(const float* __restrict__ I, int64_t n_i, int f,
-                             const double* __restrict__ cent, const double* __restrict__ cnorm,
-                             const double* __restrict__ theta, int C, uint32_t* keys, int* vals) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)C * n_i) return;
-    const int c = (int)(t / n_i);
-    const int64_t i = t - (int64_t)c * n_i;
-    const float* row = I + i * f;
+// ||i|| cos(max(theta_ic - theta_b, 0)), theta_ic by Kahan's formula on the
+// unit vectors, widened by 2^-40 ||i|| for the float64 evaluation and rounded
+// up to float32.  Workgroup (x, y): items [256 x, 256 x + 256) against
+// clusters [y cs, (y+1) cs).  With F > 0 (f <= F) the rows are staged through
+// LDS and each thread keeps its unit item in registers; the unit centroid is
+// the same for the whole wave.
+// ---------------------------------------------------------------------------
+template <int F>
+__global__ void __launch_bounds__(256) bound_kernel(const float* __restrict__ I, int64_t n_i, int f,
+                                                    const double* __restrict__ chat,
+                                                    const double* __restrict__ cnorm,
+                                                    const double* __restrict__ theta, int C, int cs,
+                                                    uint32_t* __restrict__ keys) {
+    extern __shared__ float srow[];       // F > 0: 256 x f floats, then unit centroids
+    const int64_t i0 = (int64_t)blockIdx.x * 256, i = i0 + threadIdx.x;
+    const bool on = i < n_i;
+    const int c0 = blockIdx.y * cs, c1 = min(C, c0 + cs);
+    double xh[F > 0 ? F : 1];
     double n2 = 0.0;
-    for (int j = 0; j < f; ++j) n2 += (double)row[j] * (double)row[j];
-    const double ni = sqrt(n2);
-    double b;
-    if (!(ni > 0.0)) {
-        b = 0.0;
-    } else if (!(cnorm[c] > 0.0)) {
-        b = ni;
+    if constexpr (F > 0) {
+        const int nrow = (int)min((int64_t)256, n_i - i0);
+        const float* src = I + i0 * f;
+        for (int e = threadIdx.x; e < nrow * f; e += 256) srow[e] = src[e];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const double x = (on && j < f) ? (double)srow[threadIdx.x * f + j] : 0.0;
+            xh[j] = x;
+            n2 += x * x;
+        }
     } else {
-        const double th = stable_angle(row, cent + (int64_t)c * f, f, ni, cnorm[c]);
-        b = ni * cos(fmax(th - theta[c], 0.0));
+        const float* row = I + (on ? i : 0) * f;
+        for (int j = 0; j < f; ++j) n2 += (double)row[j] * (double)row[j];
     }
-    const float b32 = round_up_f32(b + 0x1p-40 * ni * (1.0 + 0x1p-20));
-    keys[t] = desc_key(b32);
-    vals[t] = (int)i;
+    const double ni = sqrt(n2);
+    const double rinv = ni > 0.0 ? 1.0 / ni : 0.0;
+    if constexpr (F > 0) {
+#pragma unroll
+        for (int j = 0; j < F; ++j) xh[j] *= rinv;
+    }
+    const double slack = 0x1p-40 * ni * (1.0 + 0x1p-20);
+    // F > 0: the rows' LDS then holds up to 128 unit centroids at a time
+    // (256 f floats = 128 f doubles), read by the whole workgroup
+    double* sc = (double*)srow;
+    for (int cc = c0; cc < c1; cc += 128) {
+        const int nb = min(128, c1 - cc);
+        if constexpr (F > 0) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < nb * f; e += 256) sc[e] = chat[(int64_t)cc * f + e];
+            __syncthreads();
+        }
+        for (int c = cc; c < cc + nb; ++c) {
+            const double nc = cnorm[c];
+            double b;
+            if (!(ni > 0.0)) {
+                b = 0.0;
+            } else if (!(nc > 0.0)) {
+                b = ni;
+            } else {
+                double d = 0.0, s = 0.0;
+                if constexpr (F > 0) {
+                    const double* y = sc + (c - cc) * f;
+#pragma unroll
+                    for (int j = 0; j < F; ++j) {
+                        if (j < f) {
+                            const double yj = y[j];
+                            const double p = xh[j] - yj, q = xh[j] + yj;
+                            d = fma(p, p, d);
+                            s = fma(q, q, s);
+                        }
+                    }
+                } else {
+                    const double* y = chat + (int64_t)c * f;
+                    const float* row = I + (on ? i : 0) * f;
+                    for (int j = 0; j < f; ++j) {
+                        const double x = (double)row[j] * rinv;
+                        const double p = x - y[j], q = x + y[j];
+                        d = fma(p, p, d);
+                        s = fma(q, q, s);
+                    }
+                }
+                const double th = 2.0 * atan2(sqrt(d), sqrt(s));
+                b = ni * cos(fmax(th - theta[c], 0.0));
+            }
+            if (on) keys[(int64_t)c * n_i + i] = desc_key(round_up_f32(b + slack));
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort pass (8-bit digit at `shift`) over independent
-// segments of `len` (key, value) pairs; one 1024-thread workgroup per segment.
-// Elements are ranked chunk by chunk in their current order, so equal digits
-// keep their relative order.
+// Stable LSD radix sort (8-bit digit at `shift`) of C independent segments
+// of `len` (key, value) pairs, each segment split into P parts of `part`
+// pairs (grid P x C).  radix_hist_kernel counts the digits of every part;
+// radix_scatter_kernel starts each digit of part p after all smaller digits
+// of the segment and the same digit of parts before p, then ranks its pairs
+// 1024 at a time in their current order (so equal digits keep their order).
+// The first pass takes the item index as the value; the last writes the
+// padded walk lists and their float bounds.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) radix_pass_kernel(const uint32_t* __restrict__ kin,
-                                                          const int* __restrict__ vin,
-                                                          uint32_t* __restrict__ kout,
-                                                          int* __restrict__ vout, int64_t len,
-                                                          int shift) {
-    __shared__ unsigned int run[256];          // next output slot of each digit
-    __shared__ unsigned int wcnt[16][256];     // per-wave digit counts of the current chunk
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t base = (int64_t)blockIdx.x * len;
-    // histogram -> exclusive scan
-    for (int d = t; d < 16 * 256; d += 1024) (&wcnt[0][0])[d] = 0u;
-    if (t < 256) run[t] = 0u;
+__global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t len,
+                                                         int64_t part, int shift, unsigned int* hist) {
+    __shared__ unsigned int hc[256];
+    const int P = gridDim.x, p = blockIdx.x, lane = threadIdx.x & 63;
+    const int64_t seg = blockIdx.y;
+    hc[threadIdx.x] = 0u;
     __syncthreads();
-    for (int64_t i = t; i < len; i += 1024) atomicAdd(&run[(kin[base + i] >> shift) & 255u], 1u);
-    __syncthreads();
-    if (t == 0) {
-        unsigned int acc = 0u;
-        for (int d = 0; d < 256; ++d) { const unsigned int c = run[d]; run[d] = acc; acc += c; }
+    const int64_t lo = p * part, hi = min(len, lo + part);
+    const uint32_t* k = keys + seg * len;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t i0 = lo; i0 < hi; i0 += 256) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool on = i < hi;
+        const uint32_t d = on ? (k[i] >> shift) & 255u : 0u;
+        // lanes with the same digit: one LDS add per digit and wave
+        uint64_t match = __builtin_amdgcn_ballot_w64(on);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __builtin_amdgcn_ballot_w64(((d >> bit) & 1u) != 0u);
+            match &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        if (on && (match & lt) == 0ull) atomicAdd(&hc[d], (unsigned int)__builtin_popcountll(match));
     }
     __syncthreads();
+    hist[(seg * 256 + threadIdx.x) * P + p] = hc[threadIdx.x];
+}
+
+template <bool FIRST, bool LAST>
+__global__ void __launch_bounds__(1024) radix_scatter_kernel(const uint32_t* __restrict__ kin,
+                                                             const int* __restrict__ vin,
+                                                             uint32_t* __restrict__ kout,
+                                                             int* __restrict__ vout, int64_t len,
+                                                             int64_t part, int shift,
+                                                             const unsigned int* __restrict__ hist,
+                                                             int* lists, float* lbound, int64_t len_pad) {
+    __shared__ unsigned int run[256];         // next output slot of each digit
+    __shared__ unsigned int wsum[4];
+    __shared__ unsigned int wcnt[16][256];    // per-wave digit counts of the current chunk
+    __shared__ unsigned int woff[16][256];    // per-wave digit offsets of the current chunk
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int P = gridDim.x, p = blockIdx.x;
+    const int64_t seg = blockIdx.y;
+    unsigned int tot = 0u;
+    if (t < 256) {
+        const unsigned int* hs = hist + (seg * 256 + t) * P;
+        unsigned int before = 0u;
+        for (int q = 0; q < P; ++q) {
+            const unsigned int v = hs[q];
+            tot += v;
+            if (q < p) before += v;
+        }
+        run[t] = before;
+    }
+    for (int d = t; d < 16 * 256; d += 1024) (&wcnt[0][0])[d] = 0u;
+    // exclusive scan of the segment's digit totals (waves 0-3, 64 digits each)
+    unsigned int x = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (t < 256 && lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (t < 256) {
+        unsigned int pre = x - tot;
+        for (int q = 0; q < wv; ++q) pre += wsum[q];
+        run[t] += pre;
+    }
+    __syncthreads();
+    const int64_t lo = p * part, hi = min(len, lo + part);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t c0 = 0; c0 < len; c0 += 1024) {
-        const int64_t i = c0 + t;
-        const bool on = i < len;
-        const uint32_t k = on ? kin[base + i] : 0u;
-        const int v = on ? vin[base + i] : 0;
+    // the next chunk's pairs are loaded while this one is ranked
+    bool on_n = lo + t < hi;
+    uint32_t k_n = on_n ? kin[seg * len + lo + t] : 0u;
+    int v_n = FIRST ? (int)(lo + t) : (on_n ? vin[seg * len + lo + t] : 0);
+    for (int64_t c0 = lo; c0 < hi; c0 += 1024) {
+        const bool on = on_n;
+        const uint32_t k = k_n;
+        const int v = v_n;
+        {
+            const int64_t in = c0 + 1024 + t;
+            on_n = in < hi;
+            k_n = on_n ? kin[seg * len + in] : 0u;
+            v_n = FIRST ? (int)in : (on_n ? vin[seg * len + in] : 0);
+        }
         const uint32_t d = (k >> shift) & 255u;
-        // lanes of this wave holding the same digit
         uint64_t match = __builtin_amdgcn_ballot_w64(on);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -300,201 +642,238 @@ __global__ void __launch_bounds__(1024) radix_pass_kernel(const uint32_t* __rest
         const unsigned int rank_w = __builtin_popcountll(match & lt);
         if (on && rank_w == 0) wcnt[wv][d] = __builtin_popcountll(match);
         __syncthreads();
-        if (on) {
-            unsigned int pos = run[d] + rank_w;
-            for (int q = 0; q < wv; ++q) pos += wcnt[q][d];
-            kout[base + pos] = k;
-            vout[base + pos] = v;
-        }
-        __syncthreads();
         if (t < 256) {
-            unsigned int add = 0u;
-            for (int q = 0; q < 16; ++q) { add += wcnt[q][t]; wcnt[q][t] = 0u; }
-            run[t] += add;
+            unsigned int cq[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) cq[q] = wcnt[q][t];
+            unsigned int acc = run[t];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                woff[q][t] = acc;
+                wcnt[q][t] = 0u;
+                acc += cq[q];
+            }
+            run[t] = acc;
         }
         __syncthreads();
-    }
-}
-
-// Sorted (key, item) pairs -> padded walk lists and rounded-up bounds.
-__global__ void lists_kernel(const uint32_t* keys, const int* vals, int64_t n_i, int64_t n_i_pad,
-                             int C, int* lists, float* lbound) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)C * n_i_pad) return;
-    const int c = (int)(t / n_i_pad);
-    const int64_t p = t - (int64_t)c * n_i_pad;
-    if (p < n_i) {
-        lists[t] = vals[(int64_t)c * n_i + p];
-        lbound[t] = key_to_float(keys[(int64_t)c * n_i + p]);
-    } else {
-        lists[t] = -1;
-        lbound[t] = -__builtin_inff();
-    }
-}
-
-// Per (cluster, tile of 32 list entries): max C and max G of its items.
-__global__ void cblockmax_kernel(const int* lists, int64_t n_i_pad, int64_t n_blk, int C,
-                                 const float* Corig, const float* Gorig, float2* out) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)C * n_blk) return;
-    const int c = (int)(t / n_blk);
-    const int64_t b = t - (int64_t)c * n_blk;
-    float cm = 0.0f, gm = 0.0f;
-    for (int q = 0; q < kTile; ++q) {
-        const int item = lists[(int64_t)c * n_i_pad + b * kTile + q];
-        if (item >= 0) {
-            cm = fmaxf(cm, Corig[item]);
-            gm = fmaxf(gm, Gorig[item]);
+        if (on) {
+            const unsigned int pos = woff[wv][d] + rank_w;
+            if (LAST) {
+                lists[seg * len_pad + pos] = v;
+                lbound[seg * len_pad + pos] = key_to_float(k);
+            } else {
+                kout[seg * len + pos] = k;
+                vout[seg * len + pos] = v;
+            }
         }
     }
-    out[t] = make_float2(cm, gm);
+    if (LAST && p == 0) {
+        for (int64_t q = len + t; q < len_pad; q += 1024) {
+            lists[seg * len_pad + q] = -1;
+            lbound[seg * len_pad + q] = -__builtin_inff();
+        }
+    }
+}
+
+// Per item: (C_i, G_i of the three screen precisions) in one float4, so the
+// tile maxima below gather one 16-byte value per list entry.
+struct BlockMaxArgs {
+    const int* lists;
+    int64_t n_i, n_i_pad, n_blk;
+    int C;
+    const float* Corig;        // C_i (the same for every precision)
+    const float* Gorig[3];     // null for a precision without a screen
+    float4* cg4;               // n_i entries
+    float2* out[3];            // null for a precision without a screen
+};
+
+__global__ void __launch_bounds__(256) item_cg4_kernel(BlockMaxArgs a) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n_i) return;
+    a.cg4[i] = make_float4(a.Corig[i], a.Gorig[0] ? a.Gorig[0][i] : 0.0f,
+                           a.Gorig[1] ? a.Gorig[1][i] : 0.0f, a.Gorig[2] ? a.Gorig[2][i] : 0.0f);
+}
+
+// Per (cluster, tile of 32 list entries) and screen precision: max C and
+// max G of its items.
+__global__ void __launch_bounds__(256) cblockmax_kernel(BlockMaxArgs a) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)a.C * a.n_blk) return;
+    const int c = (int)(t / a.n_blk);
+    const int64_t b = t - (int64_t)c * a.n_blk;
+    const int4* li = (const int4*)(a.lists + (int64_t)c * a.n_i_pad + b * kTile);
+    float4 m = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll 2
+    for (int q = 0; q < kTile / 4; ++q) {
+        const int4 v = li[q];
+        const int it[4] = {v.x, v.y, v.z, v.w};
+        float4 g[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[r] = it[r] >= 0 ? a.cg4[it[r]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            m.x = fmaxf(m.x, g[r].x);
+            m.y = fmaxf(m.y, g[r].y);
+            m.z = fmaxf(m.z, g[r].z);
+            m.w = fmaxf(m.w, g[r].w);
+        }
+    }
+    if (a.out[0]) a.out[0][t] = make_float2(m.x, m.y);
+    if (a.out[1]) a.out[1][t] = make_float2(m.x, m.z);
+    if (a.out[2]) a.out[2][t] = make_float2(m.x, m.w);
 }
 
 // ---------------------------------------------------------------------------
 // Users grouped by cluster, in ascending user order inside each cluster (a
-// stable counting sort on the cluster id, C <= 4096): per-chunk counts,
-// per-cluster running offsets over the chunks, then a scatter that walks each
-// chunk in order, 64 users at a time, ranking equal clusters within the wave.
+// stable counting sort on the cluster id, C <= 4096): per-chunk counts
+// (cluster-major), one wave per cluster scans them over the chunks, a scan
+// over the clusters gives their starts, and one wave per chunk places its
+// users 64 at a time, ranking equal clusters within the wave by ballots on
+// the bits of the cluster id.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) group_count_kernel(const int* assign, int64_t n, int64_t chunk,
-                                                          int C, unsigned int* ccounts) {
+constexpr int kGroupChunk = 1024;
+
+__global__ void __launch_bounds__(256) group_count_kernel(const int* __restrict__ assign, int64_t n, int C,
+                                                          int nch, unsigned int* ccounts) {
     __shared__ unsigned int lc[4096];
     for (int c = threadIdx.x; c < C; c += blockDim.x) lc[c] = 0u;
     __syncthreads();
-    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const int64_t lo = (int64_t)blockIdx.x * kGroupChunk, hi = min(n, lo + kGroupChunk);
     for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) atomicAdd(&lc[assign[u]], 1u);
     __syncthreads();
-    for (int c = threadIdx.x; c < C; c += blockDim.x) ccounts[(int64_t)blockIdx.x * C + c] = lc[c];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) ccounts[(int64_t)c * nch + blockIdx.x] = lc[c];
 }
 
-// offs[k][c] = sum of ccounts[k'][c] over chunks k' < k; hist[c] = total of c
-__global__ void group_offsets_kernel(unsigned int* ccounts, int nchunks, int C, unsigned int* hist) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    unsigned int run = 0u;
-    for (int k = 0; k < nchunks; ++k) {
-        const unsigned int v = ccounts[(int64_t)k * C + c];
-        ccounts[(int64_t)k * C + c] = run;
-        run += v;
+// ccounts[c][k] -> users of cluster c in chunks before k; hist[c] = size of c
+__global__ void __launch_bounds__(64) group_scan_kernel(unsigned int* ccounts, int nch, unsigned int* hist) {
+    const int c = blockIdx.x, lane = threadIdx.x;
+    unsigned int* row = ccounts + (int64_t)c * nch;
+    unsigned int carry = 0u;
+    for (int k0 = 0; k0 < nch; k0 += 64) {
+        const int k = k0 + lane;
+        const unsigned int v = k < nch ? row[k] : 0u;
+        unsigned int x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (k < nch) row[k] = carry + x - v;
+        carry += __shfl(x, 63);
     }
-    hist[c] = run;
+    if (lane == 0) hist[c] = carry;
 }
 
-__global__ void __launch_bounds__(64) group_scatter_kernel(const int* assign, int64_t n, int64_t chunk,
-                                                           int C, const unsigned int* offs,
-                                                           const unsigned int* cstart, int* sorted) {
+__global__ void __launch_bounds__(64) group_scatter_kernel(const int* __restrict__ assign, int64_t n, int C,
+                                                           int nch, const unsigned int* __restrict__ offs,
+                                                           const unsigned int* __restrict__ cstart,
+                                                           int* sorted) {
     __shared__ unsigned int next[4096];
-    const int lane = threadIdx.x;
-    for (int c = lane; c < C; c += 64) next[c] = cstart[c] + offs[(int64_t)blockIdx.x * C + c];
+    const int lane = threadIdx.x, k = blockIdx.x;
+    for (int c = lane; c < C; c += 64) next[c] = cstart[c] + offs[(int64_t)c * nch + k];
     __syncthreads();
-    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const int64_t lo = (int64_t)k * kGroupChunk, hi = min(n, lo + kGroupChunk);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t base = lo; base < hi; base += 64) {
-        const int64_t u = base + lane;
+    const int nbits = C > 1 ? 32 - __builtin_clz((unsigned)(C - 1)) : 0;
+    int key[kGroupChunk / 64];
+#pragma unroll
+    for (int q = 0; q < kGroupChunk / 64; ++q) {
+        const int64_t u = lo + q * 64 + lane;
+        key[q] = u < hi ? assign[u] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kGroupChunk / 64; ++q) {
+        const int64_t u = lo + q * 64 + lane;
         const bool on = u < hi;
-        const int key = on ? assign[u] : -1;
-        uint64_t left = ballot(on);
-        while (left) {
-            const int leader = __builtin_ctzll(left);
-            const int k = __builtin_amdgcn_readlane(key, leader);
-            const uint64_t m = ballot(key == k);
-            if (key == k) sorted[next[k] + __builtin_popcountll(m & below)] = (int)u;
-            __syncthreads();
-            if (lane == leader) next[k] += (unsigned int)__builtin_popcountll(m);
-            __syncthreads();
-            left &= ~m;
+        uint64_t m = ballot(on);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = ((key[q] >> b) & 1) != 0;
+            const uint64_t bb = ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        // one wave: every lane reads its cursor before the group's last lane
+        // advances it (LDS accesses of a wave complete in order)
+        if (on) {
+            sorted[next[key[q]] + __builtin_popcountll(m & below)] = (int)u;
+            if ((m >> lane) == 1ull) next[key[q]] += (unsigned int)__builtin_popcountll(m);
         }
     }
 }
 
-// Fixed-point per-cluster sums over users already grouped by cluster:
-// workgroup w takes sorted positions [w * 2048, (w + 1) * 2048), thread t
-// factor t % f of rows t / f, t / f + 256 / f, ...; a thread adds its partial
-// sum to the cluster's global sum only when the cluster changes along its
-// rows, so a workgroup issues about f atomics per cluster it touches.
-constexpr int kSortedSumRows = 2048;
-
-__global__ void __launch_bounds__(256) kmeans_sum_sorted_kernel(const float* __restrict__ U,
-                                                                int64_t n_u, int f,
-                                                                const int* __restrict__ sorted,
-                                                                const int* __restrict__ assign,
-                                                                const unsigned int* absmax_bits,
-                                                                unsigned long long* sums) {
-    const int per = 256 / f;                 // rows per pass (f <= 256)
-    const int r0 = threadIdx.x / f, j = threadIdx.x - r0 * f;
-    if (r0 >= per) return;
-    const double scale = fixed_scale(n_u, *absmax_bits);
-    const int64_t lo = (int64_t)blockIdx.x * kSortedSumRows;
-    const int64_t hi = lo + kSortedSumRows < n_u ? lo + kSortedSumRows : n_u;
-    long long acc = 0;
-    int cur = -1;
-    for (int64_t p = lo + r0; p < hi; p += per) {
-        const int u = sorted[p];
-        const int c = assign[u];
-        if (c != cur) {
-            if (cur >= 0 && acc) atomicAdd(&sums[(int64_t)cur * f + j], (unsigned long long)acc);
-            acc = 0;
-            cur = c;
+// ---------------------------------------------------------------------------
+// Walk tiles: runs of up to span = 32, 64 and 128 users of one cluster.
+// Tile counts per cluster and their exclusive offsets (one workgroup, three
+// spans), then one thread per tile slot; slots past the last tile get an
+// empty tile.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) tile_offsets_kernel(const unsigned int* __restrict__ ccount, int C,
+                                                            unsigned int* toff) {
+    __shared__ unsigned int part[1024];
+    const int t = threadIdx.x;
+    for (int q = 0; q < 3; ++q) {
+        const unsigned int span = (unsigned int)kTile << q;
+        unsigned int v[4], sum = 0u;
+        for (int r = 0; r < 4; ++r) {
+            const int c = t * 4 + r;
+            v[r] = c < C ? (ccount[c] + span - 1) / span : 0u;
+            sum += v[r];
         }
-        acc += llrint((double)U[(int64_t)u * f + j] * scale);
+        part[t] = sum;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned int add = (t >= off) ? part[t - off] : 0u;
+            __syncthreads();
+            part[t] += add;
+            __syncthreads();
+        }
+        unsigned int run = part[t] - sum;
+        for (int r = 0; r < 4; ++r) {
+            toff[q * (kBuckets + 1) + t * 4 + r] = run;
+            run += v[r];
+        }
+        if (t == 1023) toff[q * (kBuckets + 1) + kBuckets] = part[t];   // total
+        __syncthreads();
     }
-    if (cur >= 0 && acc) atomicAdd(&sums[(int64_t)cur * f + j], (unsigned long long)acc);
 }
 
-__global__ void copy_counts_kernel(const unsigned int* hist, int C, unsigned int* counts) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < C) counts[c] = hist[c];
-}
+struct TileEmitArgs {
+    const unsigned int* ccount;
+    const unsigned int* cstart;
+    const unsigned int* toff;      // 3 x (kBuckets + 1)
+    int C;
+    int64_t max_tiles[3];
+    int4* tiles[3];
+};
 
-__global__ void iota_kernel(int* v, int64_t n) {
+__global__ void __launch_bounds__(256) tiles_emit_kernel(TileEmitArgs a) {
+    const int q = blockIdx.y;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < n) v[t] = (int)t;
+    if (t >= a.max_tiles[q]) return;
+    const unsigned int* to = a.toff + q * (kBuckets + 1);
+    if (t >= (int64_t)to[kBuckets]) {
+        a.tiles[q][t] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    // the last cluster whose first tile is at or before t
+    int lo = 0, hi = a.C - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)to[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const unsigned int span = (unsigned int)kTile << q;
+    const unsigned int o = (unsigned int)(t - to[lo]) * span;
+    a.tiles[q][t] = make_int4(lo, (int)(a.cstart[lo] + o), (int)min(span, a.ccount[lo] - o), 0);
 }
 
-// Users per cluster.  Each workgroup strides over many users and counts in
-// LDS, then adds its non-zero counts (same-address device atomics are slow,
-// so one per cluster and workgroup instead of one per user).
-__global__ void __launch_bounds__(256) count_kernel(const int* assign, int64_t n, int C,
-                                                    unsigned int* counts) {
-    __shared__ unsigned int lc[4096];
-    for (int c = threadIdx.x; c < C; c += blockDim.x) lc[c] = 0u;
-    __syncthreads();
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&lc[assign[t]], 1u);
-    __syncthreads();
-    for (int c = threadIdx.x; c < C; c += blockDim.x)
-        if (lc[c]) atomicAdd(&counts[c], lc[c]);
-}
-
-__global__ void set_ctrl_kernel(Ctrl* ctrl, unsigned int c, unsigned int e, unsigned int g) {
+__global__ void copy_maxima_kernel(Ctrl* ctrl, const Ctrl* src) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctrl->cmax_bits = c;
-        ctrl->emax_bits = e;
-        ctrl->gmax_bits = g;
+        ctrl->cmax_bits = src->cmax_bits;
+        ctrl->emax_bits = src->emax_bits;
+        ctrl->gmax_bits = src->gmax_bits;
     }
 }
 
 static unsigned int grid_of(int64_t n, int b = 256) { return (unsigned int)((n + b - 1) / b); }
-
-// Users grouped by cluster (ascending user order inside each cluster) into
-// `sorted`; ghist[0..C) receives the cluster sizes and ghist[4096 + c] the
-// first position of cluster c.  ccounts holds group_chunks(n_u) * C entries.
-static int64_t group_chunk(int64_t n_u) { return std::max<int64_t>(4096, (n_u + 1023) / 1024); }
-static int group_chunks(int64_t n_u) { return (int)((n_u + group_chunk(n_u) - 1) / group_chunk(n_u)); }
-
-static hipError_t group_users(const int* assign, int64_t n_u, int C, unsigned int* ccounts,
-                              unsigned int* ghist, int* sorted, hipStream_t s) {
-    const int64_t chunk = group_chunk(n_u);
-    const int nchunks = group_chunks(n_u);
-    hipError_t e = launch_zero(ghist, (size_t)2 * kBuckets * sizeof(unsigned int), s);
-    if (e != hipSuccess) return e;
-    group_count_kernel<<<nchunks, 256, 0, s>>>(assign, n_u, chunk, C, ccounts);
-    group_offsets_kernel<<<grid_of(C), 256, 0, s>>>(ccounts, nchunks, C, ghist);
-    if ((e = launch_scan4096(ghist, s)) != hipSuccess) return e;
-    group_scatter_kernel<<<nchunks, 64, 0, s>>>(assign, n_u, chunk, C, ccounts, ghist + kBuckets, sorted);
-    return hipGetLastError();
-}
 
 }  // namespace mips
 
@@ -511,9 +890,9 @@ struct mips_maximus_index {
     float* I = nullptr;
     double* cent = nullptr;
     double* theta = nullptr;
-    float* cent32 = nullptr;      // float32 centroids and their squared norms (assignment)
-    float* cnorm2 = nullptr;
-    double* cnorm = nullptr;      // float64 centroid norms (angles)
+    double* cnorm = nullptr;      // float64 centroid norms
+    double* chat = nullptr;       // unit centroids (angles)
+    float* img = nullptr;         // lane-ordered extended centroids (assignment)
     int* assign = nullptr;
     int* sorted_users = nullptr;
     int* lists = nullptr;
@@ -524,9 +903,9 @@ struct mips_maximus_index {
     float* Gorig[3] = {nullptr, nullptr, nullptr};
     int* kexp = nullptr;
     float2* cblockmax[3] = {nullptr, nullptr, nullptr};
-    unsigned int maxbits[3][3] = {};
-    Ctrl* prep_ctrl = nullptr;            // device copies of maxbits, one Ctrl per precision
-    // walk tiles for 1, 2 and 4 user blocks per wave
+    Ctrl* prep_ctrl = nullptr;            // item maxima (and NaN flag), one Ctrl per precision
+    // walk tiles for 1, 2 and 4 user blocks per wave: ntiles slots, an upper
+    // bound on the tile count; slots past the last tile hold empty tiles
     int4* tiles[3] = {nullptr, nullptr, nullptr};
     int64_t ntiles[3] = {0, 0, 0};
     std::vector<void*> allocs;
@@ -578,27 +957,40 @@ void free_index(mips_maximus_index* ix) {
     delete ix;
 }
 
-// Forgy initialisation: C distinct users drawn with a splitmix64 stream.
-std::vector<int> forgy(int64_t n_u, int C, uint64_t seed) {
-    uint64_t s = seed ^ 0x9E3779B97F4A7C15ull;
-    auto next = [&]() {
-        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    };
-    std::vector<int> out;
-    out.reserve(C);
-    std::vector<int> sorted;
-    while ((int)out.size() < C) {
-        const int cand = (int)(next() % (uint64_t)n_u);
-        auto it = std::lower_bound(sorted.begin(), sorted.end(), cand);
-        if (it != sorted.end() && *it == cand) continue;
-        sorted.insert(it, cand);
-        out.push_back(cand);
-    }
-    std::sort(out.begin(), out.end());
-    return out;
+// Nearest centroid of n_u user rows (float32 MFMA); the final pass of the
+// build also takes theta_b into theta_bits.
+hipError_t launch_assign(const mips_maximus_index* ix, const float* U, int64_t n_u, int* assign,
+                         bool final_pass, unsigned long long* theta_bits, hipStream_t s) {
+    AssignArgs a{};
+    a.U = U;
+    a.n_u = n_u;
+    a.f = ix->f;
+    a.ks = assign_ks(ix->f);
+    a.C = ix->C;
+    a.ntile = (ix->C + 31) / 32;
+    a.chunk_tiles = assign_chunk_tiles(ix->f, ix->C, final_pass);
+    a.stage = ix->f <= 64;
+    a.lds_theta = final_pass && ix->C <= 1024;
+    a.img = ix->img;
+    a.assign = assign;
+    a.chat = ix->chat;
+    a.cnorm = ix->cnorm;
+    a.theta_bits = theta_bits;
+    const size_t lds = assign_theta_bytes(ix->C, final_pass) + (size_t)a.chunk_tiles * a.ks * 256 +
+                       assign_stage_bytes(ix->f);
+    const int64_t n_ublk = (n_u + 31) / 32;
+    const unsigned grid = (unsigned)std::min<int64_t>((n_ublk + kAssignWaves - 1) / kAssignWaves, 1024);
+#define ASSIGN_LAUNCH(KS)                                                          \
+    do {                                                                           \
+        if (final_pass) assign_mfma_kernel<KS, true><<<grid, 256, lds, s>>>(a);    \
+        else assign_mfma_kernel<KS, false><<<grid, 256, lds, s>>>(a);              \
+    } while (0)
+    if (a.ks <= 16) ASSIGN_LAUNCH(16);
+    else if (a.ks <= 32) ASSIGN_LAUNCH(32);
+    else if (a.ks <= 64) ASSIGN_LAUNCH(64);
+    else ASSIGN_LAUNCH(132);
+#undef ASSIGN_LAUNCH
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -611,26 +1003,47 @@ std::vector<int> forgy(int64_t n_u, int C, uint64_t seed) {
 // vector tries its nearest centroid; the others take the exact path.
 // ---------------------------------------------------------------------------
 __global__ void qcover_kernel(const float* __restrict__ Uq, int64_t n_q, int f,
-                              const int* __restrict__ qassign, const double* __restrict__ cent,
+                              const int* __restrict__ qassign, const double* __restrict__ chat,
                               const double* __restrict__ cnorm, const double* __restrict__ theta,
                               unsigned int* ccount, int* uflag, int* flist, Ctrl* ctrl) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n_q) return;
     const float* row = Uq + q * f;
-    double n2 = 0.0;
+    // the sums of the build's final assignment pass, in the same order (the
+    // coordinates j with (j / 2) % 2 == 0 and those with (j / 2) % 2 == 1
+    // summed apart, each in ascending j, then added), so an indexed user
+    // queried as a vector measures the same angle
+    double n2a = 0.0, n2b = 0.0;
     bool finite = true;
     for (int j = 0; j < f; ++j) {
+        const double x = (double)row[j];
         finite = finite && __builtin_isfinite(row[j]);
-        n2 += (double)row[j] * (double)row[j];
+        if (((j >> 1) & 1) == 0) n2a = fma(x, x, n2a);
+        else n2b = fma(x, x, n2b);
     }
+    const double n2 = n2a + n2b;
     const int c = qassign[q];
     bool covered = false;
     if (finite && n2 > 0.0) {
         if (!(cnorm[c] > 0.0)) {
             covered = true;                       // theta_b = pi: the bound is ||i||
         } else {
-            const double th = stable_angle(row, cent + (int64_t)c * f, f, sqrt(n2), cnorm[c]);
-            covered = th <= theta[c];
+            // Kahan's angle on the unit vectors, as for theta_b
+            const double rinv = 1.0 / sqrt(n2);
+            const double* y = chat + (int64_t)c * f;
+            double da = 0.0, sa = 0.0, db = 0.0, sb = 0.0;
+            for (int j = 0; j < f; ++j) {
+                const double x = (double)row[j] * rinv;
+                const double p = x - y[j], r = x + y[j];
+                if (((j >> 1) & 1) == 0) {
+                    da = fma(p, p, da);
+                    sa = fma(r, r, sa);
+                } else {
+                    db = fma(p, p, db);
+                    sb = fma(r, r, sb);
+                }
+            }
+            covered = 2.0 * atan2(sqrt(da + db), sqrt(sa + sb)) <= theta[c];
         }
     }
     if (!finite) atomicOr(&ctrl->nonfinite, 1u);
@@ -697,6 +1110,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     ix->n_blk = (n_i + kTile - 1) / kTile;
     ix->n_i_pad = ix->n_blk * kTile;
     ix->shared_blocks = block_items > 0 ? (block_items + kTile - 1) / kTile : 1;
+    const int ks = assign_ks(f), ntile = (C + 31) / 32;
 
     hipError_t e = hipSuccess;
     auto fail_hip = [&](const char* what) {
@@ -709,70 +1123,54 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     // copies of the inputs
     TRY(dalloc(ix, &ix->U, (size_t)n_u * f), "alloc U");
     TRY(dalloc(ix, &ix->I, (size_t)n_i * f), "alloc I");
-    TRY(hipMemcpyAsync(ix->U, U, (size_t)n_u * f * sizeof(float), hipMemcpyDeviceToDevice, s), "copy U");
     TRY(hipMemcpyAsync(ix->I, I, (size_t)n_i * f * sizeof(float), hipMemcpyDeviceToDevice, s), "copy I");
 
     // ---- k-means (Section III-A) -----------------------------------------
-    unsigned int* absmax = nullptr;
-    unsigned long long* sums = nullptr;
-    unsigned int* counts = nullptr;
-    float* cent32 = nullptr;
-    float* cnorm2 = nullptr;
-    double* cnorm = nullptr;
-    int* init_idx = nullptr;
     TRY(dalloc(ix, &ix->cent, (size_t)C * f), "alloc centroids");
-    TRY(dalloc(ix, &ix->theta, (size_t)C), "alloc theta");
+    TRY(dalloc(ix, &ix->chat, (size_t)C * f), "alloc centroids");
+    TRY(dalloc(ix, &ix->cnorm, (size_t)C), "alloc");
+    TRY(dalloc(ix, &ix->img, (size_t)ntile * ks * 64), "alloc");
     TRY(dalloc(ix, &ix->assign, (size_t)n_u), "alloc assign");
-    TRY(dalloc(ix, &absmax, 1), "alloc");
-    TRY(dalloc(ix, &sums, (size_t)C * f), "alloc");
-    TRY(dalloc(ix, &counts, (size_t)C), "alloc");
-    unsigned int *ccounts = nullptr, *ghist = nullptr;
     TRY(dalloc(ix, &ix->sorted_users, (size_t)n_u), "alloc");
-    TRY(dalloc(ix, &ccounts, (size_t)group_chunks(n_u) * C), "alloc");
-    TRY(dalloc(ix, &ghist, (size_t)2 * kBuckets), "alloc");
-    // sums in LDS per workgroup when C x f fits, else over users grouped by cluster
-    const bool lds_sums = (int64_t)C * f <= 4096;
-    TRY(dalloc(ix, &cent32, (size_t)C * f), "alloc");
-    TRY(dalloc(ix, &cnorm2, (size_t)C), "alloc");
-    TRY(dalloc(ix, &cnorm, (size_t)C), "alloc");
-    TRY(dalloc(ix, &init_idx, (size_t)C), "alloc");
-    {
-        const std::vector<int> pick = forgy(n_u, C, seed);
-        TRY(hipMemcpyAsync(init_idx, pick.data(), C * sizeof(int), hipMemcpyHostToDevice, s), "copy init");
-        TRY(hipStreamSynchronize(s), "sync");   // `pick` leaves scope
-    }
-    TRY(launch_zero(absmax, sizeof(unsigned int), s), "zero");
-    absmax_kernel<<<256, 256, 0, s>>>(ix->U, n_u * f, absmax);
-    gather_rows_kernel<<<grid_of((int64_t)C * f), 256, 0, s>>>(ix->U, f, init_idx, C, ix->cent);
-    const size_t lds_assign = (size_t)64 * f * sizeof(float);
+    // state that starts at zero, cleared by one launch
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t z_absmax = 0, z_sums = al(4), z_counts = z_sums + al((size_t)C * f * 8),
+                 z_theta = z_counts + al((size_t)C * 4), z_ghist = z_theta + al((size_t)C * 8),
+                 z_end = z_ghist + al((size_t)2 * kBuckets * 4);
+    unsigned char* zb = nullptr;
+    TRY(dalloc(ix, &zb, z_end), "alloc");
+    unsigned int* absmax = (unsigned int*)(zb + z_absmax);
+    unsigned long long* sums = (unsigned long long*)(zb + z_sums);
+    unsigned int* counts = (unsigned int*)(zb + z_counts);
+    ix->theta = (double*)(zb + z_theta);
+    unsigned int* ghist = (unsigned int*)(zb + z_ghist);
+    TRY(launch_zero(zb, z_end, s), "zero");
+    // the index's copy of U and max |u| (the fixed-point scale of the sums)
+    copy_absmax_kernel<<<std::min(grid_of((n_u * f) / 16 + 1), 2048u), 256, 0, s>>>(U, ix->U, n_u * f, absmax);
+    forgy_kernel<<<grid_of((int64_t)C * f), 256, 0, s>>>(ix->U, n_u, f, C, seed, ix->cent);
+    // sums: clusters in slices whose (cluster, factor) sums fit in LDS beside
+    // the assignments of up to kSumMaxRows rows (64 KB in all)
+    const size_t per_c = (size_t)f * 8 + 4;
+    int cs = (int)std::min<int64_t>(C, (65536 - 4 * kSumMaxRows) / per_c);
+    cs = (C + (C + cs - 1) / cs - 1) / ((C + cs - 1) / cs);    // even slices
+    const int nsl = (C + cs - 1) / cs;
+    int64_t rows = std::min<int64_t>(kSumMaxRows, std::max<int64_t>(256, (n_u * nsl + 511) / 512));
+    rows &= ~(int64_t)3;
+    const unsigned sum_gx = (unsigned)((n_u + rows - 1) / rows);
+    const size_t sum_lds = (size_t)cs * f * 8 + (size_t)cs * 4 + (size_t)rows * 4;
     for (int it = 0; it <= kmeans_iters; ++it) {
-        cent_prep_kernel<<<grid_of(C), 256, 0, s>>>(ix->cent, C, f, cent32, cnorm2);
-        assign_kernel<<<grid_of(n_u), 256, lds_assign, s>>>(ix->U, n_u, f, cent32, cnorm2, C, ix->assign);
-        if (it == kmeans_iters) break;   // final assignment after the last update
-        TRY(launch_zero(sums, (size_t)C * f * sizeof(unsigned long long), s), "zero");
-        TRY(launch_zero(counts, (size_t)C * sizeof(unsigned int), s), "zero");
-        if (lds_sums) {
-            kmeans_sum_kernel<<<grid_of(n_u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, absmax, sums, counts, C);
-        } else {
-            TRY(group_users(ix->assign, n_u, C, ccounts, ghist, ix->sorted_users, s), "grouping");
-            kmeans_sum_sorted_kernel<<<grid_of(n_u, kSortedSumRows), 256, 0, s>>>(
-                ix->U, n_u, f, ix->sorted_users, ix->assign, absmax, sums);
-            copy_counts_kernel<<<grid_of(C), 256, 0, s>>>(ghist, C, counts);
-        }
+        cent_prep_kernel<<<ntile, 256, f <= 254 ? (size_t)32 * f * 8 : 0, s>>>(ix->cent, C, f, ks, ix->img,
+                                                                               ix->cnorm, ix->chat, counts);
+        const bool last = it == kmeans_iters;
+        // the final assignment also gives theta_b (Algorithm 1, ConstructIndex)
+        TRY(launch_assign(ix, ix->U, n_u, ix->assign, last, (unsigned long long*)ix->theta, s), "assignment");
+        if (last) break;
+        kmeans_sum_kernel<<<dim3(sum_gx, nsl), 256, sum_lds, s>>>(ix->U, n_u, f, ix->assign, absmax, rows,
+                                                                 cs, sums, counts, C);
         kmeans_update_kernel<<<grid_of((int64_t)C * f), 256, 0, s>>>(ix->cent, C, f, sums, counts, absmax, n_u);
     }
+    theta_fix_kernel<<<grid_of(C), 256, 0, s>>>(ix->cnorm, C, ix->theta);
     TRY(hipGetLastError(), "k-means");
-
-    // ---- theta_b (Algorithm 1, ConstructIndex) ----------------------------
-    cnorm_kernel<<<grid_of(C), 256, 0, s>>>(ix->cent, C, f, cnorm);
-    TRY(launch_zero(ix->theta, (size_t)C * sizeof(double), s), "zero");
-    theta_kernel<<<std::min(grid_of(n_u), 1024u), 256, 0, s>>>(ix->U, n_u, f, ix->assign, ix->cent,
-                                                               cnorm, C, (unsigned long long*)ix->theta);
-    theta_fix_kernel<<<grid_of(C), 256, 0, s>>>(cnorm, C, ix->theta);
-    TRY(hipGetLastError(), "theta_b");
-    ix->cent32 = cent32;
-    ix->cnorm2 = cnorm2;
-    ix->cnorm = cnorm;
 
     // ---- bounds and per-cluster lists --------------------------------------
     {
@@ -783,20 +1181,50 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         TRY(dalloc(ix, &k1, tot), "alloc keys");
         TRY(dalloc(ix, &v0, tot), "alloc vals");
         TRY(dalloc(ix, &v1, tot), "alloc vals");
-        bound_kernel<<<grid_of((int64_t)tot), 256, 0, s>>>(ix->I, n_i, f, ix->cent, cnorm, ix->theta,
-                                                           C, k0, v0);
-        for (int pass = 0; pass < 4; ++pass) {
-            const bool even = (pass & 1) == 0;
-            radix_pass_kernel<<<C, 1024, 0, s>>>(even ? k0 : k1, even ? v0 : v1, even ? k1 : k0,
-                                                  even ? v1 : v0, n_i, 8 * pass);
+        const unsigned nbx = grid_of(n_i);
+        const int want = std::max(1, std::min(C, 1024 / (int)nbx));
+        const int bcs = (C + want - 1) / want;
+        const unsigned bsl = (unsigned)((C + bcs - 1) / bcs);
+        const int F = f <= 16 ? 16 : (f <= 32 ? 32 : (f <= 64 ? 64 : 0));
+        const size_t blds = F ? (size_t)256 * f * 4 : 0;
+        const dim3 bg(nbx, bsl);
+        switch (F) {
+            case 16: bound_kernel<16><<<bg, 256, blds, s>>>(ix->I, n_i, f, ix->chat, ix->cnorm, ix->theta, C, bcs, k0); break;
+            case 32: bound_kernel<32><<<bg, 256, blds, s>>>(ix->I, n_i, f, ix->chat, ix->cnorm, ix->theta, C, bcs, k0); break;
+            case 64: bound_kernel<64><<<bg, 256, blds, s>>>(ix->I, n_i, f, ix->chat, ix->cnorm, ix->theta, C, bcs, k0); break;
+            default: bound_kernel<0><<<bg, 256, 0, s>>>(ix->I, n_i, f, ix->chat, ix->cnorm, ix->theta, C, bcs, k0); break;
         }
+        TRY(hipGetLastError(), "bounds");
         TRY(dalloc(ix, &ix->lists, (size_t)C * ix->n_i_pad), "alloc lists");
         TRY(dalloc(ix, &ix->lbound, (size_t)C * ix->n_i_pad), "alloc bounds");
-        lists_kernel<<<grid_of((int64_t)C * ix->n_i_pad), 256, 0, s>>>(k0, v0, n_i, ix->n_i_pad, C,
-                                                                       ix->lists, ix->lbound);
+        const int P = (int)std::max<int64_t>(1, std::min<int64_t>(512 / C, (n_i + 1023) / 1024));
+        const int64_t part = (n_i + P - 1) / P;
+        unsigned int* rh = nullptr;
+        TRY(dalloc(ix, &rh, (size_t)C * 256 * P), "alloc");
+        const dim3 rg(P, C);
+        radix_hist_kernel<<<rg, 256, 0, s>>>(k0, n_i, part, 0, rh);
+        radix_scatter_kernel<true, false><<<rg, 1024, 0, s>>>(k0, nullptr, k1, v1, n_i, part, 0, rh, nullptr, nullptr, 0);
+        radix_hist_kernel<<<rg, 256, 0, s>>>(k1, n_i, part, 8, rh);
+        radix_scatter_kernel<false, false><<<rg, 1024, 0, s>>>(k1, v1, k0, v0, n_i, part, 8, rh, nullptr, nullptr, 0);
+        radix_hist_kernel<<<rg, 256, 0, s>>>(k0, n_i, part, 16, rh);
+        radix_scatter_kernel<false, false><<<rg, 1024, 0, s>>>(k0, v0, k1, v1, n_i, part, 16, rh, nullptr, nullptr, 0);
+        radix_hist_kernel<<<rg, 256, 0, s>>>(k1, n_i, part, 24, rh);
+        radix_scatter_kernel<false, true><<<rg, 1024, 0, s>>>(k1, v1, nullptr, nullptr, n_i, part, 24, rh,
+                                                              ix->lists, ix->lbound, ix->n_i_pad);
         TRY(hipGetLastError(), "lists");
-        // users grouped by the final assignment
-        TRY(group_users(ix->assign, n_u, C, ccounts, ghist, ix->sorted_users, s), "user grouping");
+    }
+
+    // ---- users grouped by the final assignment ------------------------------
+    {
+        const int nch = (int)((n_u + kGroupChunk - 1) / kGroupChunk);
+        unsigned int* ccounts = nullptr;
+        TRY(dalloc(ix, &ccounts, (size_t)C * nch), "alloc");
+        group_count_kernel<<<nch, 256, 0, s>>>(ix->assign, n_u, C, nch, ccounts);
+        group_scan_kernel<<<C, 64, 0, s>>>(ccounts, nch, ghist);
+        TRY(launch_scan4096(ghist, s), "scan");
+        group_scatter_kernel<<<nch, 64, 0, s>>>(ix->assign, n_u, C, nch, ccounts, ghist + kBuckets,
+                                                ix->sorted_users);
+        TRY(hipGetLastError(), "user grouping");
     }
 
     // ---- screen copies of the items for every precision --------------------
@@ -808,6 +1236,18 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         TRY(dalloc(ix, &Etmp, (size_t)n_i), "alloc");
         TRY(dalloc(ix, &ix->kexp, (size_t)n_i), "alloc");
         TRY(launch_zero(tctrl, 3 * sizeof(Ctrl), s), "zero");
+        BlockMaxArgs bm{};
+        bm.lists = ix->lists;
+        bm.n_i = n_i;
+        bm.n_i_pad = ix->n_i_pad;
+        bm.n_blk = ix->n_blk;
+        bm.C = C;
+        float4* cg4 = nullptr;
+        TRY(dalloc(ix, &cg4, (size_t)n_i), "alloc");
+        bm.cg4 = cg4;
+        bool any = false;
+        ItemPrepArgs ias[3] = {};
+        const ItemPrepArgs* iap[3] = {nullptr, nullptr, nullptr};
         for (int prec = 0; prec < 3; ++prec) {
             ScreenPlan p;
             make_screen_plan(n_u, n_i, f, 1, prec, true, &p);
@@ -818,7 +1258,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
             TRY(dalloc(ix, &ix->Corig[prec], (size_t)n_i), "alloc");
             TRY(dalloc(ix, &ix->Gorig[prec], (size_t)n_i), "alloc");
             TRY(dalloc(ix, &ix->cblockmax[prec], (size_t)C * ix->n_blk), "alloc");
-            ItemPrepArgs ia{};
+            ItemPrepArgs& ia = ias[prec];
             ia.I = ix->I;
             ia.n_i = n_i;
             ia.n_blk = ix->n_blk;
@@ -833,54 +1273,59 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
             ia.qrow = q;
             ia.ctrl = tctrl + prec;
             if (p.fast) {
-                TRY(launch_item_prep(prec, ia, false, s), "item screen copies");
-                cblockmax_kernel<<<grid_of((int64_t)C * ix->n_blk), 256, 0, s>>>(
-                    ix->lists, ix->n_i_pad, ix->n_blk, C, ix->Corig[prec], ix->Gorig[prec],
-                    ix->cblockmax[prec]);
-                TRY(hipGetLastError(), "tile maxima");
+                iap[prec] = &ia;
+                bm.Corig = ix->Corig[prec];
+                bm.Gorig[prec] = ix->Gorig[prec];
+                bm.out[prec] = ix->cblockmax[prec];
+                any = true;
             } else if (prec == 0) {
                 // no screen for these sizes (every query takes the exact path):
                 // only the finiteness check of I is needed
                 TRY(launch_nonfinite_scan(ix->I, 0, ix->I, n_i * f, tctrl, s), "finite check");
             }
         }
-        Ctrl h[3];
-        TRY(hipMemcpyAsync(h, tctrl, sizeof(h), hipMemcpyDeviceToHost, s), "read maxima");
-        TRY(hipStreamSynchronize(s), "sync");
-        for (int prec = 0; prec < 3; ++prec) {
-            ix->maxbits[prec][0] = h[prec].cmax_bits;
-            ix->maxbits[prec][1] = h[prec].emax_bits;
-            ix->maxbits[prec][2] = h[prec].gmax_bits;
-            if (h[prec].nonfinite) {
-                free_index(ix);
-                return fail(MIPS_ERR_NONFINITE, "I holds NaN or Inf");
-            }
+        if (any) {
+            TRY(launch_item_stats3(iap, s), "item screen copies");
+            item_cg4_kernel<<<grid_of(n_i), 256, 0, s>>>(bm);
+            cblockmax_kernel<<<grid_of((int64_t)C * ix->n_blk), 256, 0, s>>>(bm);
+            TRY(hipGetLastError(), "tile maxima");
         }
     }
 
     // ---- walk tiles: runs of up to 32*UB users of one cluster --------------
     {
-        TRY(launch_zero(counts, (size_t)C * sizeof(unsigned int), s), "zero");
-        count_kernel<<<std::min(grid_of(n_u), 256u), 256, 0, s>>>(ix->assign, n_u, C, counts);
-        std::vector<unsigned int> hc(C);
-        TRY(hipMemcpyAsync(hc.data(), counts, C * sizeof(unsigned int), hipMemcpyDeviceToHost, s), "read counts");
-        TRY(hipStreamSynchronize(s), "sync");
-        const int ubs[3] = {1, 2, 4};
+        unsigned int* toff = nullptr;
+        TRY(dalloc(ix, &toff, (size_t)3 * (kBuckets + 1)), "alloc");
+        tile_offsets_kernel<<<1, 1024, 0, s>>>(ghist, C, toff);
+        TileEmitArgs ta{};
+        ta.ccount = ghist;
+        ta.cstart = ghist + kBuckets;
+        ta.toff = toff;
+        ta.C = C;
+        int64_t most = 0;
         for (int q = 0; q < 3; ++q) {
-            const int span = kTile * ubs[q];
-            std::vector<int4> tl;
-            int64_t start = 0;
-            for (int c = 0; c < C; ++c) {
-                for (int64_t o = 0; o < (int64_t)hc[c]; o += span)
-                    tl.push_back(make_int4(c, (int)(start + o), (int)std::min<int64_t>(span, hc[c] - o), 0));
-                start += hc[c];
-            }
-            if (tl.empty()) tl.push_back(make_int4(0, 0, 0, 0));
-            ix->ntiles[q] = (int64_t)tl.size();
-            TRY(dalloc(ix, &ix->tiles[q], tl.size()), "alloc tiles");
-            TRY(hipMemcpyAsync(ix->tiles[q], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice, s), "copy tiles");
+            const int64_t span = (int64_t)kTile << q;
+            ix->ntiles[q] = (n_u + span - 1) / span + C;
+            TRY(dalloc(ix, &ix->tiles[q], (size_t)ix->ntiles[q]), "alloc tiles");
+            ta.max_tiles[q] = ix->ntiles[q];
+            ta.tiles[q] = ix->tiles[q];
+            most = std::max(most, ix->ntiles[q]);
         }
+        tiles_emit_kernel<<<dim3(grid_of(most), 3), 256, 0, s>>>(ta);
+        TRY(hipGetLastError(), "walk tiles");
+    }
+
+    // ---- the one host check: NaN or Inf in I --------------------------------
+    {
+        Ctrl h[3];
+        TRY(hipMemcpyAsync(h, ix->prep_ctrl, sizeof(h), hipMemcpyDeviceToHost, s), "read flags");
         TRY(hipStreamSynchronize(s), "sync");
+        for (int prec = 0; prec < 3; ++prec) {
+            if (h[prec].nonfinite) {
+                free_index(ix);
+                return fail(MIPS_ERR_NONFINITE, "I holds NaN or Inf");
+            }
+        }
     }
 #undef TRY
     *out_index = ix;
@@ -947,8 +1392,7 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
                           double* fbkeys, int32_t* out_idx, double* out_score, bool want_stats,
                           hipStream_t s) {
     hipError_t e;
-    set_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, ix->maxbits[precision][0], ix->maxbits[precision][1],
-                                     ix->maxbits[precision][2]);
+    copy_maxima_kernel<<<1, 64, 0, s>>>(ctrl, ix->prep_ctrl + precision);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "set maxima");
     ScreenArgs a{};
     a.U = U;
@@ -1154,9 +1598,9 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     if (p.fast) {
         PhaseTimer t(MIPS_PHASE_WALK, s);
         const int C = ix->C, f = ix->f, span = kTile * p.UB;
-        const size_t lds_assign = (size_t)64 * f * sizeof(float);
-        assign_kernel<<<grid_of(n_q), 256, lds_assign, s>>>(Uq, n_q, f, ix->cent32, ix->cnorm2, C, qassign);
-        qcover_kernel<<<grid_of(n_q), 256, 0, s>>>(Uq, n_q, f, qassign, ix->cent, ix->cnorm, ix->theta,
+        if ((e = launch_assign(ix, Uq, n_q, qassign, false, nullptr, s)) != hipSuccess)
+            return hip_fail(e, "assignment");
+        qcover_kernel<<<grid_of(n_q), 256, 0, s>>>(Uq, n_q, f, qassign, ix->chat, ix->cnorm, ix->theta,
                                                    ccount, uflag, flist, ctrl);
         if ((e = launch_scan4096(ccount, s)) != hipSuccess) return hip_fail(e, "scan");
         qtile_count_kernel<<<grid_of(C), 256, 0, s>>>(ccount, C, span, tcount);

@@ -47,90 +47,99 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 constexpr int kPrepLanes = 16;
 constexpr int kPrepPer = 128 / kPrepLanes;      // factors per lane at f_pad = 128
 
+// Screen copy, norms and bucket of item i for precision PREC from its
+// factors x (lane q of the item's 16 holds factors q, q + 16, ...), whose
+// float64 sum of squares s2, largest magnitude and finiteness are already
+// reduced over the 16 lanes; (C, E, G) raise the running maxima.
 template <int PREC>
-__global__ void __launch_bounds__(256) item_stats_kernel(ItemPrepArgs a) {
-    __shared__ unsigned int smax[3][4];
-    const int q = threadIdx.x & (kPrepLanes - 1);
-    // the global maxima are reduced over the whole workgroup (one atomic per
-    // workgroup: same-address atomics serialise)
-    unsigned int cb = 0u, eb = 0u, gb = 0u;
-    for (int64_t base = (int64_t)blockIdx.x * (256 / kPrepLanes); base < a.n_i;
-         base += (int64_t)gridDim.x * (256 / kPrepLanes)) {
-        const int64_t i = base + threadIdx.x / kPrepLanes;
-        const bool on = i < a.n_i;
-        const float* row = a.I + (on ? i : 0) * a.f;
-        float x[kPrepPer];
-        double s2 = 0.0;
-        float amax = 0.0f;
-        bool finite = true;
+__device__ __forceinline__ void item_stats_one(const ItemPrepArgs& a, int64_t i, bool on, int q,
+                                               const float (&x)[kPrepPer], double s2, float amax,
+                                               bool finite, unsigned int& cb, unsigned int& eb,
+                                               unsigned int& gb) {
+    int k = 0;
+    if (PREC == PREC_FP8) k = e4m3_row_scale_exp(amax);
+    double r2 = 0.0, q2 = 0.0;
 #pragma unroll
-        for (int e = 0; e < kPrepPer; ++e) {
-            const int j = q + e * kPrepLanes;
-            x[e] = (on && j < a.f) ? row[j] : 0.0f;
-            finite = finite && __builtin_isfinite(x[e]);
-            s2 += (double)x[e] * (double)x[e];
-            amax = fmaxf(amax, fabsf(x[e]));
-        }
-        for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
-            s2 += __shfl_xor(s2, off, kPrepLanes);
-            amax = fmaxf(amax, __shfl_xor(amax, off, kPrepLanes));
-            // every lane must take part in the exchange (no short-circuit)
-            const int fp = __shfl_xor((int)finite, off, kPrepLanes);
-            finite = finite && (fp != 0);
-        }
-        int k = 0;
-        if (PREC == PREC_FP8) k = e4m3_row_scale_exp(amax);
-        double r2 = 0.0, q2 = 0.0;
-#pragma unroll
-        for (int e = 0; e < kPrepPer; ++e) {
-            const int j = q + e * kPrepLanes;
-            if (!on || j >= a.f_pad) continue;
-            if (PREC == PREC_FP32) {
-                ((float*)a.qrow)[i * a.f_pad + j] = x[e];
-            } else if (PREC == PREC_BF16) {
-                const uint16_t hb = f32_to_bf16_bits(x[e]);
-                const double d = (double)bf16_bits_to_f32(hb);
-                r2 += ((double)x[e] - d) * ((double)x[e] - d);
-                q2 += d * d;
-                ((uint16_t*)a.qrow)[i * a.f_pad + j] = hb;
-            } else {
-                const uint32_t b = e4m3_encode(__builtin_ldexpf(x[e], -k));
-                const double d = __builtin_ldexp((double)e4m3_decode(b), k);
-                r2 += ((double)x[e] - d) * ((double)x[e] - d);
-                q2 += d * d;
-                ((uint8_t*)a.qrow)[i * a.f_pad + j] = (uint8_t)b;
-            }
-        }
+    for (int e = 0; e < kPrepPer; ++e) {
+        const int j = q + e * kPrepLanes;
+        if (!on || j >= a.f_pad) continue;
         if (PREC == PREC_FP32) {
-            q2 = s2;
+            ((float*)a.qrow)[i * a.f_pad + j] = x[e];
+        } else if (PREC == PREC_BF16) {
+            const uint16_t hb = f32_to_bf16_bits(x[e]);
+            const double d = (double)bf16_bits_to_f32(hb);
+            r2 += ((double)x[e] - d) * ((double)x[e] - d);
+            q2 += d * d;
+            ((uint16_t*)a.qrow)[i * a.f_pad + j] = hb;
         } else {
-            for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
-                r2 += __shfl_xor(r2, off, kPrepLanes);
-                q2 += __shfl_xor(q2, off, kPrepLanes);
-            }
+            const uint32_t b = e4m3_encode(__builtin_ldexpf(x[e], -k));
+            const double d = __builtin_ldexp((double)e4m3_decode(b), k);
+            r2 += ((double)x[e] - d) * ((double)x[e] - d);
+            q2 += d * d;
+            ((uint8_t*)a.qrow)[i * a.f_pad + j] = (uint8_t)b;
         }
-        float C = norm_up_f32(sqrt(s2));
-        float E = norm_up_f32(sqrt(q2));
-        float G = (PREC == PREC_FP32) ? 0.0f : norm_up_f32(sqrt(r2) + (double)a.gamma * sqrt(q2));
-        if (!finite || !on) { C = 0.0f; E = 0.0f; G = 0.0f; }
-        if (on && q == 0) {
-            if (PREC == PREC_FP8) a.kexp[i] = k;
-            a.Corig[i] = C;
-            a.Gorig[i] = G;
-            a.Eorig[i] = E;
-            if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
-            if (a.bucket) {
-                // descending ||i||: 16 buckets per octave from the float bits
-                int bk = (kBuckets - 1) - (int)(__float_as_uint(C) >> 19);
-                bk = bk < 0 ? 0 : (bk >= kBuckets ? kBuckets - 1 : bk);
-                a.bucket[i] = bk;
-            }
-        }
-        // all values are >= 0, so their bit patterns order as integers
-        cb = max(cb, __float_as_uint(C));
-        eb = max(eb, __float_as_uint(E));
-        gb = max(gb, __float_as_uint(G));
     }
+    if (PREC == PREC_FP32) {
+        q2 = s2;
+    } else {
+        for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
+            r2 += __shfl_xor(r2, off, kPrepLanes);
+            q2 += __shfl_xor(q2, off, kPrepLanes);
+        }
+    }
+    float C = norm_up_f32(sqrt(s2));
+    float E = norm_up_f32(sqrt(q2));
+    float G = (PREC == PREC_FP32) ? 0.0f : norm_up_f32(sqrt(r2) + (double)a.gamma * sqrt(q2));
+    if (!finite || !on) { C = 0.0f; E = 0.0f; G = 0.0f; }
+    if (on && q == 0) {
+        if (PREC == PREC_FP8) a.kexp[i] = k;
+        a.Corig[i] = C;
+        a.Gorig[i] = G;
+        a.Eorig[i] = E;
+        if (!finite) atomicOr(&a.ctrl->nonfinite, 1u);
+        if (a.bucket) {
+            // descending ||i||: 16 buckets per octave from the float bits
+            int bk = (kBuckets - 1) - (int)(__float_as_uint(C) >> 19);
+            bk = bk < 0 ? 0 : (bk >= kBuckets ? kBuckets - 1 : bk);
+            a.bucket[i] = bk;
+        }
+    }
+    // all values are >= 0, so their bit patterns order as integers
+    cb = max(cb, __float_as_uint(C));
+    eb = max(eb, __float_as_uint(E));
+    gb = max(gb, __float_as_uint(G));
+}
+
+// Item i's factors for its 16 lanes and their float64 sum of squares,
+// largest magnitude and finiteness, reduced over the 16 lanes.
+__device__ __forceinline__ void item_load(const ItemPrepArgs& a, int64_t i, bool on, int q,
+                                          float (&x)[kPrepPer], double& s2, float& amax,
+                                          bool& finite) {
+    const float* row = a.I + (on ? i : 0) * a.f;
+    s2 = 0.0;
+    amax = 0.0f;
+    finite = true;
+#pragma unroll
+    for (int e = 0; e < kPrepPer; ++e) {
+        const int j = q + e * kPrepLanes;
+        x[e] = (on && j < a.f) ? row[j] : 0.0f;
+        finite = finite && __builtin_isfinite(x[e]);
+        s2 += (double)x[e] * (double)x[e];
+        amax = fmaxf(amax, fabsf(x[e]));
+    }
+    for (int off = kPrepLanes / 2; off >= 1; off >>= 1) {
+        s2 += __shfl_xor(s2, off, kPrepLanes);
+        amax = fmaxf(amax, __shfl_xor(amax, off, kPrepLanes));
+        // every lane must take part in the exchange (no short-circuit)
+        const int fp = __shfl_xor((int)finite, off, kPrepLanes);
+        finite = finite && (fp != 0);
+    }
+}
+
+// The global maxima are reduced over the whole workgroup (one atomic per
+// workgroup and value: same-address atomics serialise).
+__device__ __forceinline__ void item_maxima_flush(Ctrl* ctrl, unsigned int cb, unsigned int eb,
+                                                  unsigned int gb, unsigned int (&smax)[3][4]) {
     for (int off = 32; off >= 1; off >>= 1) {
         cb = max(cb, (unsigned int)__shfl_xor((int)cb, off));
         eb = max(eb, (unsigned int)__shfl_xor((int)eb, off));
@@ -147,10 +156,55 @@ __global__ void __launch_bounds__(256) item_stats_kernel(ItemPrepArgs a) {
         unsigned int m[3];
         for (int v = 0; v < 3; ++v)
             m[v] = max(max(smax[v][0], smax[v][1]), max(smax[v][2], smax[v][3]));
-        atomicMax(&a.ctrl->cmax_bits, m[0]);
-        atomicMax(&a.ctrl->emax_bits, m[1]);
-        atomicMax(&a.ctrl->gmax_bits, m[2]);
+        atomicMax(&ctrl->cmax_bits, m[0]);
+        atomicMax(&ctrl->emax_bits, m[1]);
+        atomicMax(&ctrl->gmax_bits, m[2]);
     }
+    __syncthreads();
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) item_stats_kernel(ItemPrepArgs a) {
+    __shared__ unsigned int smax[3][4];
+    const int q = threadIdx.x & (kPrepLanes - 1);
+    unsigned int cb = 0u, eb = 0u, gb = 0u;
+    for (int64_t base = (int64_t)blockIdx.x * (256 / kPrepLanes); base < a.n_i;
+         base += (int64_t)gridDim.x * (256 / kPrepLanes)) {
+        const int64_t i = base + threadIdx.x / kPrepLanes;
+        const bool on = i < a.n_i;
+        float x[kPrepPer];
+        double s2;
+        float amax;
+        bool finite;
+        item_load(a, i, on, q, x, s2, amax, finite);
+        item_stats_one<PREC>(a, i, on, q, x, s2, amax, finite, cb, eb, gb);
+    }
+    item_maxima_flush(a.ctrl, cb, eb, gb, smax);
+}
+
+// The three screen precisions of the same items in one pass over I (a
+// Maximus index keeps all three); `mask` bit p enables precision p.
+__global__ void __launch_bounds__(256) item_stats3_kernel(ItemPrepArgs a0, ItemPrepArgs a1,
+                                                          ItemPrepArgs a2, int mask) {
+    __shared__ unsigned int smax[3][4];
+    const int q = threadIdx.x & (kPrepLanes - 1);
+    unsigned int cb[3] = {0u, 0u, 0u}, eb[3] = {0u, 0u, 0u}, gb[3] = {0u, 0u, 0u};
+    for (int64_t base = (int64_t)blockIdx.x * (256 / kPrepLanes); base < a0.n_i;
+         base += (int64_t)gridDim.x * (256 / kPrepLanes)) {
+        const int64_t i = base + threadIdx.x / kPrepLanes;
+        const bool on = i < a0.n_i;
+        float x[kPrepPer];
+        double s2;
+        float amax;
+        bool finite;
+        item_load(a0, i, on, q, x, s2, amax, finite);
+        if (mask & 1) item_stats_one<PREC_FP32>(a0, i, on, q, x, s2, amax, finite, cb[0], eb[0], gb[0]);
+        if (mask & 2) item_stats_one<PREC_BF16>(a1, i, on, q, x, s2, amax, finite, cb[1], eb[1], gb[1]);
+        if (mask & 4) item_stats_one<PREC_FP8>(a2, i, on, q, x, s2, amax, finite, cb[2], eb[2], gb[2]);
+    }
+    if (mask & 1) item_maxima_flush(a0.ctrl, cb[0], eb[0], gb[0], smax);
+    if (mask & 2) item_maxima_flush(a1.ctrl, cb[1], eb[1], gb[1], smax);
+    if (mask & 4) item_maxima_flush(a2.ctrl, cb[2], eb[2], gb[2], smax);
 }
 
 // Exclusive scan of the bucket counts (one workgroup of 1024 threads).
@@ -308,6 +362,23 @@ hipError_t launch_scan4096(unsigned int* hist, hipStream_t s) {
 hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* I,
                                  int64_t ni_elems, Ctrl* ctrl, hipStream_t s) {
     nonfinite_scan_kernel<<<dim3(1024), dim3(256), 0, s>>>(U, nu_elems, I, ni_elems, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_stats3(const ItemPrepArgs* const (&a)[3], hipStream_t s) {
+    int mask = 0;
+    const ItemPrepArgs* any = nullptr;
+    for (int p = 0; p < 3; ++p) {
+        if (!a[p]) continue;
+        if (a[p]->f_pad > 128 || a[p]->f > a[p]->f_pad) return hipErrorInvalidValue;
+        mask |= 1 << p;
+        any = a[p];
+    }
+    if (!any) return hipSuccess;
+    const int64_t groups = (any->n_i + 256 / kPrepLanes - 1) / (256 / kPrepLanes);
+    const unsigned ns = (unsigned)(groups < 256 ? groups : 256);
+    item_stats3_kernel<<<ns, 256, 0, s>>>(a[0] ? *a[0] : *any, a[1] ? *a[1] : *any, a[2] ? *a[2] : *any,
+                                          mask);
     return hipGetLastError();
 }
 
