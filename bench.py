@@ -165,7 +165,11 @@ def extras(mips, torch, np, mipsgen, oracle_topk):
         holder = {}
         def build():
             holder["ix"] = mips.maximus_build(Ut, It, C, 3, 0, 0)
-        tb = timed(torch, build, 3)
+        tbs = []
+        for _ in range(3):
+            holder.pop("ix", None)        # the previous index is freed outside the timed call
+            tbs.append(timed(torch, build, 1))
+        tb = sorted(tbs)[1]
         ix = holder["ix"]
         tq = timed(torch, lambda: ix.query(10, "bf16"), 5)
         mips.profile_read()

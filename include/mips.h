@@ -43,6 +43,13 @@
  *    stats->nonfinite_input); the outputs are then unspecified.
  *  - Calls that share a workspace must not overlap in time (different
  *    streams need different workspaces).
+ *  - Device memory: mips_maximus_build and mips_optimus_topk take their
+ *    device memory from a block cache owned by the library (hipMalloc
+ *    blocks).  Released blocks stay cached, up to 4 GiB per process, and
+ *    are reused by later calls, so repeated builds do not map device pages
+ *    again.  A block is released only when no work on the device can still
+ *    use it.  mips_topk_backward takes stream-ordered scratch
+ *    (hipMallocAsync / hipFreeAsync on `stream`).
  */
 #ifndef MIPS_H
 #define MIPS_H
@@ -146,8 +153,10 @@ typedef struct mips_maximus_index mips_maximus_index; /* opaque; owns device mem
  *                to the item tile (32)
  *   out_index    receives the index; free it with mips_maximus_free()
  * The index copies U and I (and their screen copies); the caller may free them
- * afterwards.  Synchronises `stream` before returning (the index records sizes
- * computed on the device).  Returns MIPS_ERR_NOMEM if device memory runs out. */
+ * afterwards.  Everything runs on the device; `stream` is synchronised once,
+ * at the end, to report NaN or Inf in I (MIPS_ERR_NONFINITE).  Index memory
+ * and build temporaries come from the library's block cache (see "Device
+ * memory" above).  Returns MIPS_ERR_NOMEM if device memory runs out. */
 int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i, int32_t f,
                        int32_t n_clusters, int32_t kmeans_iters, uint64_t seed,
                        int32_t block_items, void* stream, mips_maximus_index** out_index);
@@ -184,7 +193,9 @@ int mips_maximus_query_users(const mips_maximus_index* index, const float* Uq, i
                              void* workspace, size_t workspace_bytes, void* stream,
                              mips_stats* stats);
 
-/* Release the index and its device memory (NULL is ignored). */
+/* Release the index (NULL is ignored): waits until the device is idle (a
+ * query on any stream may still read the index), then returns its memory to
+ * the library's block cache. */
 void mips_maximus_free(mips_maximus_index* index);
 
 /* Index description, for tests and reports (host memory, NULL fields skipped).
@@ -202,8 +213,9 @@ int mips_maximus_export(const mips_maximus_index* index, int32_t* n_clusters, in
  * methods on a seeded random sample of users, extrapolates each to the whole
  * batch (the index estimate includes its construction time), finishes the
  * remaining users with the faster method and reuses the sampled answers.
- * The sample is systematic: users floor((k + phase) n_u / s), k < s, with a
- * seeded random phase (evenly spread over the user order).
+ * The sample is systematic: users floor((k n_u + off) / s), k < s, with a
+ * seeded random offset 0 <= off < n_u (evenly spread over the user order),
+ * chosen on the device.
  * Both methods are exact: the result is the mips_bmm_topk contract whatever
  * the choice.
  *   sample_users  0 = default: max(131072, n_u / 100), at most n_u (a sample

@@ -166,7 +166,7 @@ static BmmLayout bmm_layout(const ScreenPlan& p) {
         L.packed = take((size_t)p.n_i_pad * p.f_pad * esz);
         L.pscale = take((size_t)p.n_i_pad * 4);
         L.blockmax = take((size_t)p.n_blk * 8);
-        L.cgpos = take((size_t)p.n_i_pad * 8);
+        L.cgpos = take((size_t)p.n_i_pad * 16);
         L.tailmax = take((size_t)p.n_blk * 4);
         if (casc) {
             L.qrowb = take((size_t)p.n_i * cascade_stride(p.f) * 2);
@@ -242,6 +242,92 @@ int noalloc_scratch(void** out) {
     }
     *out = g_scratch_ptr[dev];
     return MIPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory of indexes and of Optimus' scratch: blocks from hipMalloc,
+// kept in a per-process cache when released, so that repeated builds, frees
+// and Optimus calls reuse them instead of mapping device pages again (a
+// hipMalloc of tens of MB costs about 0.1 ms).  A release is only made once
+// no work on the device can still use the block.  The cache keeps at most
+// kCacheLimit bytes; beyond that the oldest blocks are freed.
+// ---------------------------------------------------------------------------
+struct CachedBlock {
+    int dev;
+    void* p;
+    size_t bytes;
+};
+static std::mutex g_cache_mu;
+static std::vector<CachedBlock> g_cache;
+static size_t g_cache_bytes = 0;
+constexpr size_t kCacheLimit = (size_t)4 << 30;
+
+static size_t cache_round(size_t bytes) {
+    const size_t g = bytes >= ((size_t)1 << 20) ? ((size_t)1 << 20) : 4096;
+    return (std::max<size_t>(bytes, 1) + g - 1) / g * g;
+}
+
+hipError_t cache_alloc(void** p, size_t* bytes_out, size_t bytes) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    bytes = cache_round(bytes);
+    {
+        // smallest cached block of this device that holds the request
+        // without wasting more than half of itself
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        int best = -1;
+        for (int k = 0; k < (int)g_cache.size(); ++k) {
+            const CachedBlock& c = g_cache[k];
+            if (c.dev == dev && c.bytes >= bytes && c.bytes <= 2 * bytes &&
+                (best < 0 || c.bytes < g_cache[best].bytes))
+                best = k;
+        }
+        if (best >= 0) {
+            *p = g_cache[best].p;
+            *bytes_out = g_cache[best].bytes;
+            g_cache_bytes -= g_cache[best].bytes;
+            g_cache.erase(g_cache.begin() + best);
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        // give the cached blocks of this device back and try once more
+        (void)hipGetLastError();
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> g(g_cache_mu);
+            for (int k = (int)g_cache.size() - 1; k >= 0; --k) {
+                if (g_cache[k].dev != dev) continue;
+                drop.push_back(g_cache[k].p);
+                g_cache_bytes -= g_cache[k].bytes;
+                g_cache.erase(g_cache.begin() + k);
+            }
+        }
+        for (void* q : drop) (void)hipFree(q);
+        e = hipMalloc(p, bytes);
+    }
+    if (e == hipSuccess) *bytes_out = bytes;
+    return e;
+}
+
+void cache_release(void* p, size_t bytes) {
+    if (!p) return;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::vector<void*> drop;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        g_cache.push_back({dev, p, bytes});
+        g_cache_bytes += bytes;
+        while (g_cache_bytes > kCacheLimit && !g_cache.empty()) {
+            drop.push_back(g_cache.front().p);
+            g_cache_bytes -= g_cache.front().bytes;
+            g_cache.erase(g_cache.begin());
+        }
+    }
+    for (void* q : drop) (void)hipFree(q);
 }
 
 }  // namespace mips
@@ -411,7 +497,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
             ia.packed = ws + L.packed;
             ia.pscale = (int*)(ws + L.pscale);
             ia.blockmax = (float2*)(ws + L.blockmax);
-            ia.cgpos = (float2*)(ws + L.cgpos);
+            ia.cgpos = (float4*)(ws + L.cgpos);
             ia.ctrl = ctrl;
             if ((e = launch_item_prep(precision, ia, true, s)) != hipSuccess)
                 return hip_fail(e, "item preparation");
@@ -468,7 +554,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
         a.packed = ws + L.packed;
         a.pscale = (const int*)(ws + L.pscale);
         a.blockmax = (const float2*)(ws + L.blockmax);
-        a.cgpos = (const float2*)(ws + L.cgpos);
+        a.cgpos = (const float4*)(ws + L.cgpos);
         a.tailmax = (const float*)(ws + L.tailmax);
         a.prune = prune;
         a.perm = (const int*)(ws + L.perm);

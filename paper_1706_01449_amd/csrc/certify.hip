@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             for (int j = 0; j < a.f; ++j) unorm += (double)urow[j] * (double)urow[j];
             unorm = sqrt(unorm);
         }
-        // the user's two lists (lanes n and n+32 of its screen wave), lane-major
+        // the user's two lists (lanes n and n+32 of its screen wave)
         const int64_t base0 = cand_at(ublk, n, 0, a.cap), base1 = cand_at(ublk, n + 32, 0, a.cap);
         for (int j0 = g; j0 < tot; j0 += 4 * G) {
             int2 e[4];
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             for (int q = 0; q < 4; ++q) {
                 const int j = j0 + q * G;
                 e[q] = make_int2(0, -1);
-                if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j : base1 + (j - m0)];
+                if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * kCandStride : base1 + (j - m0) * kCandStride];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) e[q].y = cand_item(a, e[q].y);
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     for (int base = 0; base < tot; base += 64) {
         const int j = base + lane;
         int2 e = make_int2(0, -1);
-        if (j < tot) e = a.cand[(j < c0) ? base0 + j : base1 + (j - c0)];
+        if (j < tot) e = a.cand[(j < c0) ? base0 + j * kCandStride : base1 + (j - c0) * kCandStride];
         e.y = cand_item(a, e.y);
         bool keep = false;
         if (e.y >= 0) {

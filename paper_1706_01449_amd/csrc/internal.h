@@ -37,10 +37,14 @@ __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap, bool sto
                       : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1)));
 }
 
-// Candidate lists, lane-major: entry j of lane l of user block blk sits at
-// ((blk 64) + l) cap + j (each lane appends to a list of its own).
+// Candidate lists, element-major: entry j of lane l of user block blk sits
+// at (blk cap + j) 64 + l (each lane appends to a list of its own; the j-th
+// entries of a block's 64 lanes are contiguous, so a wave reading one entry
+// per lane reads 512 contiguous bytes).  Entries of one lane are
+// kCandStride apart.
+constexpr int kCandStride = 64;
 __host__ __device__ inline int64_t cand_at(int64_t blk, int lane, int j, int cap) {
-    return ((blk * 64) + lane) * (int64_t)cap + j;
+    return ((blk * cap + j) << 6) + lane;
 }
 inline size_t cand_bytes(int64_t n_ublk, int cap) { return (size_t)n_ublk * 64 * cap * 8; }
 
@@ -93,7 +97,7 @@ struct ScreenArgs {
     const int* pscale;        // FP8: E8M0 scale byte per sorted position
     const float2* blockmax;   // per item tile: (max C, max G)
     const int* perm;          // sorted position -> item index (-1 past the last item)
-    const float2* cgpos;      // (C_i, G_i) by sorted position
+    const float4* cgpos;      // (C_i, G_i, item bits, 0) by sorted position
     const float* tailmax;     // per tile: max ||i|| over this and all later tiles
     int prune;                // norm pruning: a user stops once ||u|| tailmax < tau_u
     // Maximus walk
@@ -165,7 +169,7 @@ struct ItemPrepArgs {
     void* packed;
     int* pscale;
     float2* blockmax;
-    float2* cgpos;            // (C_i, G_i) by sorted position (nullable)
+    float4* cgpos;            // (C_i, G_i, item bits, 0) by sorted position (nullable)
     Ctrl* ctrl;
 };
 
@@ -198,6 +202,13 @@ hipError_t launch_nonfinite_scan(const float* U, int64_t nu_elems, const float* 
                                  int64_t ni_elems, Ctrl* ctrl, hipStream_t s);
 
 // Host-side helpers of the C ABI.
+// Device memory of the current device from the library's block cache: the
+// block holds at least `bytes` (*bytes_out: its size, to pass back on
+// release).  Release a block only when no work on the device can still use
+// it.
+hipError_t cache_alloc(void** p, size_t* bytes_out, size_t bytes);
+void cache_release(void* p, size_t bytes);
+
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 

@@ -287,10 +287,12 @@ __global__ void __launch_bounds__(256) assign_mfma_kernel(AssignArgs a) {
 
 // Per 32-centroid tile (rows staged through LDS): float32 squared norms,
 // float64 norms, unit centroids and the lane-ordered image of the extended
-// centroids; also clears the cluster counts for the next update.
+// centroids; also clears the cluster counts for the next update and, before
+// the final assignment, theta_b.
 __global__ void __launch_bounds__(256) cent_prep_kernel(const double* __restrict__ cent, int C, int f,
                                                         int ks, float* img, double* cnorm,
-                                                        double* chat, unsigned int* counts) {
+                                                        double* chat, unsigned int* counts,
+                                                        double* theta_zero) {
     extern __shared__ double srows[];          // 32 x f
     __shared__ float n2s[32];
     __shared__ double nrm[32];
@@ -316,6 +318,7 @@ __global__ void __launch_bounds__(256) cent_prep_kernel(const double* __restrict
             }
             cnorm[c] = sqrt(s64);
             if (counts) counts[c] = 0u;
+            if (theta_zero) theta_zero[c] = 0.0;
         }
         n2s[tid] = s;
         nrm[tid] = sqrt(s64);
@@ -725,7 +728,8 @@ __global__ void __launch_bounds__(256) cblockmax_kernel(BlockMaxArgs a) {
 
 // ---------------------------------------------------------------------------
 // Users grouped by cluster, in ascending user order inside each cluster (a
-// stable counting sort on the cluster id, C <= 4096): per-chunk counts
+// stable counting sort on the cluster id, C <= 4096; a negative id leaves
+// the user out): per-chunk counts
 // (cluster-major), one wave per cluster scans them over the chunks, a scan
 // over the clusters gives their starts, and one wave per chunk places its
 // users 64 at a time, ranking equal clusters within the wave by ballots on
@@ -739,7 +743,10 @@ __global__ void __launch_bounds__(256) group_count_kernel(const int* __restrict_
     for (int c = threadIdx.x; c < C; c += blockDim.x) lc[c] = 0u;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * kGroupChunk, hi = min(n, lo + kGroupChunk);
-    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) atomicAdd(&lc[assign[u]], 1u);
+    for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
+        const int c = assign[u];
+        if (c >= 0) atomicAdd(&lc[c], 1u);
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < C; c += blockDim.x) ccounts[(int64_t)c * nch + blockIdx.x] = lc[c];
 }
@@ -783,7 +790,7 @@ __global__ void __launch_bounds__(64) group_scatter_kernel(const int* __restrict
 #pragma unroll
     for (int q = 0; q < kGroupChunk / 64; ++q) {
         const int64_t u = lo + q * 64 + lane;
-        const bool on = u < hi;
+        const bool on = u < hi && key[q] >= 0;
         uint64_t m = ballot(on);
         for (int b = 0; b < nbits; ++b) {
             const bool bit = ((key[q] >> b) & 1) != 0;
@@ -908,51 +915,38 @@ struct mips_maximus_index {
     // bound on the tile count; slots past the last tile hold empty tiles
     int4* tiles[3] = {nullptr, nullptr, nullptr};
     int64_t ntiles[3] = {0, 0, 0};
-    std::vector<void*> allocs;
-    char* arena = nullptr;                // free space of the current chunk
-    size_t arena_left = 0;
+    // device memory of the index and the build's temporaries (released when
+    // the build ends): blocks of the library's cache, with their sizes
+    std::vector<std::pair<void*, size_t>> allocs, tmp;
 };
 
 namespace {
 
 int ub_slot(int UB) { return UB == 1 ? 0 : (UB == 2 ? 1 : 2); }
 
-// Device memory of the index comes from a few chunks of kIndexChunk bytes
-// (one hipMalloc and one hipFree each), carved into 256-byte aligned pieces;
-// a piece of at least a chunk gets an allocation of its own.
-constexpr size_t kIndexChunk = (size_t)32 << 20;
-
+// Device memory of the index and of its build temporaries comes from the
+// library's block cache (a released index leaves its blocks for the next).
 template <typename T>
-hipError_t dalloc(mips_maximus_index* ix, T** p, size_t count) {
-    const size_t bytes = ((count * sizeof(T) > 0 ? count * sizeof(T) : 1) + 255) & ~(size_t)255;
-    if (bytes >= kIndexChunk) {
-        void* q = nullptr;
-        const hipError_t e = hipMalloc(&q, bytes);
-        if (e != hipSuccess) return e;
-        ix->allocs.push_back(q);
-        *p = (T*)q;
-        return hipSuccess;
-    }
-    if (bytes > ix->arena_left) {
-        void* q = nullptr;
-        const hipError_t e = hipMalloc(&q, kIndexChunk);
-        if (e != hipSuccess) return e;
-        ix->allocs.push_back(q);
-        ix->arena = (char*)q;
-        ix->arena_left = kIndexChunk;
-    }
-    *p = (T*)ix->arena;
-    ix->arena += bytes;
-    ix->arena_left -= bytes;
+hipError_t dalloc(mips_maximus_index* ix, T** p, size_t count, bool temp = false) {
+    void* q = nullptr;
+    size_t got = 0;
+    const hipError_t e = cache_alloc(&q, &got, count * sizeof(T));
+    if (e != hipSuccess) return e;
+    (temp ? ix->tmp : ix->allocs).push_back({q, got});
+    *p = (T*)q;
     return hipSuccess;
 }
 
+// Waits for all work on the index's device (a query on any stream may still
+// read it), then returns its blocks to the cache.
 void free_index(mips_maximus_index* ix) {
     if (!ix) return;
     int cur = 0;
     const bool have = hipGetDevice(&cur) == hipSuccess;
     if (have) (void)hipSetDevice(ix->device);
-    for (void* p : ix->allocs) (void)hipFree(p);
+    (void)hipDeviceSynchronize();
+    for (auto& q : ix->allocs) cache_release(q.first, q.second);
+    for (auto& q : ix->tmp) cache_release(q.first, q.second);
     if (have) (void)hipSetDevice(cur);
     delete ix;
 }
@@ -1003,9 +997,9 @@ hipError_t launch_assign(const mips_maximus_index* ix, const float* U, int64_t n
 // vector tries its nearest centroid; the others take the exact path.
 // ---------------------------------------------------------------------------
 __global__ void qcover_kernel(const float* __restrict__ Uq, int64_t n_q, int f,
-                              const int* __restrict__ qassign, const double* __restrict__ chat,
+                              int* __restrict__ qassign, const double* __restrict__ chat,
                               const double* __restrict__ cnorm, const double* __restrict__ theta,
-                              unsigned int* ccount, int* uflag, int* flist, Ctrl* ctrl) {
+                              int* uflag, int* flist, Ctrl* ctrl) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n_q) return;
     const float* row = Uq + q * f;
@@ -1047,37 +1041,12 @@ __global__ void qcover_kernel(const float* __restrict__ Uq, int64_t n_q, int f,
         }
     }
     if (!finite) atomicOr(&ctrl->nonfinite, 1u);
-    if (covered) {
-        atomicAdd(&ccount[c], 1u);
-    } else {
+    if (!covered) {
+        qassign[q] = -1;                          // left out of the grouping
         uflag[q] = 1;
         const unsigned int k = atomicAdd(&ctrl->fb_count, 1u);
         flist[k] = (int)q;
     }
-}
-
-__global__ void qscatter_kernel(int64_t n_q, const int* __restrict__ qassign,
-                                const int* __restrict__ uflag, unsigned int* offs, int* sorted) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n_q || uflag[q]) return;
-    const unsigned int pos = atomicAdd(&offs[qassign[q]], 1u);
-    sorted[pos] = (int)q;
-}
-
-// tiles per cluster for runs of `span` users
-__global__ void qtile_count_kernel(const unsigned int* ccount, int C, int span, unsigned int* tcount) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    tcount[c] = (ccount[c] + span - 1) / span;
-}
-
-__global__ void qtiles_kernel(const unsigned int* ccount, const unsigned int* cstart,
-                              const unsigned int* toff, int C, int span, int4* tiles) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    const unsigned int n = ccount[c];
-    for (unsigned int o = 0, t = 0; o < n; o += span, ++t)
-        tiles[toff[c] + t] = make_int4(c, (int)(cstart[c] + o), (int)min((unsigned int)span, n - o), 0);
 }
 
 extern "C" {
@@ -1135,14 +1104,13 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     // state that starts at zero, cleared by one launch
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t z_absmax = 0, z_sums = al(4), z_counts = z_sums + al((size_t)C * f * 8),
-                 z_theta = z_counts + al((size_t)C * 4), z_ghist = z_theta + al((size_t)C * 8),
-                 z_end = z_ghist + al((size_t)2 * kBuckets * 4);
+                 z_ghist = z_counts + al((size_t)C * 4), z_end = z_ghist + al((size_t)2 * kBuckets * 4);
+    TRY(dalloc(ix, &ix->theta, (size_t)C), "alloc theta");
     unsigned char* zb = nullptr;
-    TRY(dalloc(ix, &zb, z_end), "alloc");
+    TRY(dalloc(ix, &zb, z_end, true), "alloc");
     unsigned int* absmax = (unsigned int*)(zb + z_absmax);
     unsigned long long* sums = (unsigned long long*)(zb + z_sums);
     unsigned int* counts = (unsigned int*)(zb + z_counts);
-    ix->theta = (double*)(zb + z_theta);
     unsigned int* ghist = (unsigned int*)(zb + z_ghist);
     TRY(launch_zero(zb, z_end, s), "zero");
     // the index's copy of U and max |u| (the fixed-point scale of the sums)
@@ -1159,9 +1127,9 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     const unsigned sum_gx = (unsigned)((n_u + rows - 1) / rows);
     const size_t sum_lds = (size_t)cs * f * 8 + (size_t)cs * 4 + (size_t)rows * 4;
     for (int it = 0; it <= kmeans_iters; ++it) {
-        cent_prep_kernel<<<ntile, 256, f <= 254 ? (size_t)32 * f * 8 : 0, s>>>(ix->cent, C, f, ks, ix->img,
-                                                                               ix->cnorm, ix->chat, counts);
         const bool last = it == kmeans_iters;
+        cent_prep_kernel<<<ntile, 256, f <= 254 ? (size_t)32 * f * 8 : 0, s>>>(
+            ix->cent, C, f, ks, ix->img, ix->cnorm, ix->chat, counts, last ? ix->theta : nullptr);
         // the final assignment also gives theta_b (Algorithm 1, ConstructIndex)
         TRY(launch_assign(ix, ix->U, n_u, ix->assign, last, (unsigned long long*)ix->theta, s), "assignment");
         if (last) break;
@@ -1177,10 +1145,10 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         uint32_t *k0 = nullptr, *k1 = nullptr;
         int *v0 = nullptr, *v1 = nullptr;
         const size_t tot = (size_t)C * n_i;
-        TRY(dalloc(ix, &k0, tot), "alloc keys");
-        TRY(dalloc(ix, &k1, tot), "alloc keys");
-        TRY(dalloc(ix, &v0, tot), "alloc vals");
-        TRY(dalloc(ix, &v1, tot), "alloc vals");
+        TRY(dalloc(ix, &k0, tot, true), "alloc keys");
+        TRY(dalloc(ix, &k1, tot, true), "alloc keys");
+        TRY(dalloc(ix, &v0, tot, true), "alloc vals");
+        TRY(dalloc(ix, &v1, tot, true), "alloc vals");
         const unsigned nbx = grid_of(n_i);
         const int want = std::max(1, std::min(C, 1024 / (int)nbx));
         const int bcs = (C + want - 1) / want;
@@ -1200,7 +1168,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         const int P = (int)std::max<int64_t>(1, std::min<int64_t>(512 / C, (n_i + 1023) / 1024));
         const int64_t part = (n_i + P - 1) / P;
         unsigned int* rh = nullptr;
-        TRY(dalloc(ix, &rh, (size_t)C * 256 * P), "alloc");
+        TRY(dalloc(ix, &rh, (size_t)C * 256 * P, true), "alloc");
         const dim3 rg(P, C);
         radix_hist_kernel<<<rg, 256, 0, s>>>(k0, n_i, part, 0, rh);
         radix_scatter_kernel<true, false><<<rg, 1024, 0, s>>>(k0, nullptr, k1, v1, n_i, part, 0, rh, nullptr, nullptr, 0);
@@ -1218,7 +1186,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     {
         const int nch = (int)((n_u + kGroupChunk - 1) / kGroupChunk);
         unsigned int* ccounts = nullptr;
-        TRY(dalloc(ix, &ccounts, (size_t)C * nch), "alloc");
+        TRY(dalloc(ix, &ccounts, (size_t)C * nch, true), "alloc");
         group_count_kernel<<<nch, 256, 0, s>>>(ix->assign, n_u, C, nch, ccounts);
         group_scan_kernel<<<C, 64, 0, s>>>(ccounts, nch, ghist);
         TRY(launch_scan4096(ghist, s), "scan");
@@ -1233,7 +1201,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         float* Etmp = nullptr;
         TRY(dalloc(ix, &tctrl, 3), "alloc");
         ix->prep_ctrl = tctrl;
-        TRY(dalloc(ix, &Etmp, (size_t)n_i), "alloc");
+        TRY(dalloc(ix, &Etmp, (size_t)n_i, true), "alloc");
         TRY(dalloc(ix, &ix->kexp, (size_t)n_i), "alloc");
         TRY(launch_zero(tctrl, 3 * sizeof(Ctrl), s), "zero");
         BlockMaxArgs bm{};
@@ -1243,7 +1211,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         bm.n_blk = ix->n_blk;
         bm.C = C;
         float4* cg4 = nullptr;
-        TRY(dalloc(ix, &cg4, (size_t)n_i), "alloc");
+        TRY(dalloc(ix, &cg4, (size_t)n_i, true), "alloc");
         bm.cg4 = cg4;
         bool any = false;
         ItemPrepArgs ias[3] = {};
@@ -1295,7 +1263,7 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
     // ---- walk tiles: runs of up to 32*UB users of one cluster --------------
     {
         unsigned int* toff = nullptr;
-        TRY(dalloc(ix, &toff, (size_t)3 * (kBuckets + 1)), "alloc");
+        TRY(dalloc(ix, &toff, (size_t)3 * (kBuckets + 1), true), "alloc");
         tile_offsets_kernel<<<1, 1024, 0, s>>>(ghist, C, toff);
         TileEmitArgs ta{};
         ta.ccount = ghist;
@@ -1327,6 +1295,9 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
             }
         }
     }
+    // the stream has finished with the temporaries
+    for (auto& q : ix->tmp) cache_release(q.first, q.second);
+    ix->tmp.clear();
 #undef TRY
     *out_index = ix;
     return MIPS_OK;
@@ -1481,9 +1452,10 @@ int check_query_args(const mips_maximus_index* ix, int32_t K, int32_t precision,
 // Workspace of a vector query: sizes in one place for the size function and
 // the query.
 struct QueryLayout {
-    size_t ctrl, uflag, ccount, tcount, tiles, zero_end;
-    size_t flist, uscal, qassign, sorted, cnt, cand, fbkeys, total;
+    size_t ctrl, uflag, ccount, zero_end;
+    size_t toff, tiles, flist, uscal, qassign, sorted, ccounts, cnt, cand, fbkeys, total;
     int64_t max_tiles;
+    int nch;
 };
 
 QueryLayout query_layout(const mips_maximus_index* ix, const ScreenPlan& p, int64_t n_q) {
@@ -1493,16 +1465,18 @@ QueryLayout query_layout(const mips_maximus_index* ix, const ScreenPlan& p, int6
     const int span = kTile * p.UB;
     L.max_tiles = p.fast ? (n_q + span - 1) / span + ix->C : 0;
     const int64_t n_ublk = L.max_tiles * p.UB;
+    L.nch = (int)((n_q + kGroupChunk - 1) / kGroupChunk);
     L.ctrl = take(sizeof(Ctrl));
     L.uflag = take((size_t)n_q * 4);
-    L.ccount = take(2 * kBuckets * sizeof(unsigned int));
-    L.tcount = take(2 * kBuckets * sizeof(unsigned int));
-    L.tiles = take((size_t)std::max<int64_t>(L.max_tiles, 1) * sizeof(int4));
+    L.ccount = take(2 * kBuckets * sizeof(unsigned int));      // cluster sizes, then starts
     L.zero_end = o;
+    L.toff = take(3 * (kBuckets + 1) * sizeof(unsigned int));
+    L.tiles = take((size_t)std::max<int64_t>(L.max_tiles, 1) * sizeof(int4));
     L.flist = take((size_t)n_q * 4);
     L.uscal = take((size_t)n_q * 16);
     L.qassign = take((size_t)n_q * 4);
     L.sorted = take((size_t)n_q * 4);
+    L.ccounts = take((size_t)ix->C * L.nch * sizeof(unsigned int));
     L.cnt = take((size_t)n_ublk * 64 * 4);
     L.cand = take(cand_bytes(n_ublk, p.cap));
     L.fbkeys = take((size_t)p.fb_grid * ix->n_i * 8);
@@ -1587,7 +1561,8 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     Ctrl* ctrl = (Ctrl*)(ws + L.ctrl);
     int* uflag = (int*)(ws + L.uflag);
     unsigned int* ccount = (unsigned int*)(ws + L.ccount);   // counts, then starts
-    unsigned int* tcount = (unsigned int*)(ws + L.tcount);   // tile counts, then offsets
+    unsigned int* toff = (unsigned int*)(ws + L.toff);       // tile offsets per span
+    unsigned int* ccounts = (unsigned int*)(ws + L.ccounts);
     int4* tiles = (int4*)(ws + L.tiles);
     int* flist = (int*)(ws + L.flist);
     float4* uscal = (float4*)(ws + L.uscal);
@@ -1597,16 +1572,26 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     if ((e = launch_zero(ws, L.zero_end, s)) != hipSuccess) return hip_fail(e, "zero");
     if (p.fast) {
         PhaseTimer t(MIPS_PHASE_WALK, s);
-        const int C = ix->C, f = ix->f, span = kTile * p.UB;
+        const int C = ix->C, f = ix->f;
         if ((e = launch_assign(ix, Uq, n_q, qassign, false, nullptr, s)) != hipSuccess)
             return hip_fail(e, "assignment");
         qcover_kernel<<<grid_of(n_q), 256, 0, s>>>(Uq, n_q, f, qassign, ix->chat, ix->cnorm, ix->theta,
-                                                   ccount, uflag, flist, ctrl);
+                                                   uflag, flist, ctrl);
+        // covered vectors grouped by cluster (stable), then their walk tiles
+        group_count_kernel<<<L.nch, 256, 0, s>>>(qassign, n_q, C, L.nch, ccounts);
+        group_scan_kernel<<<C, 64, 0, s>>>(ccounts, L.nch, ccount);
         if ((e = launch_scan4096(ccount, s)) != hipSuccess) return hip_fail(e, "scan");
-        qtile_count_kernel<<<grid_of(C), 256, 0, s>>>(ccount, C, span, tcount);
-        if ((e = launch_scan4096(tcount, s)) != hipSuccess) return hip_fail(e, "scan");
-        qtiles_kernel<<<grid_of(C), 256, 0, s>>>(ccount, ccount + kBuckets, tcount + kBuckets, C, span, tiles);
-        qscatter_kernel<<<grid_of(n_q), 256, 0, s>>>(n_q, qassign, uflag, ccount + kBuckets, sorted);
+        group_scatter_kernel<<<L.nch, 64, 0, s>>>(qassign, n_q, C, L.nch, ccounts, ccount + kBuckets, sorted);
+        tile_offsets_kernel<<<1, 1024, 0, s>>>(ccount, C, toff);
+        TileEmitArgs ta{};
+        ta.ccount = ccount;
+        ta.cstart = ccount + kBuckets;
+        ta.toff = toff;
+        ta.C = C;
+        const int slot = ub_slot(p.UB);
+        ta.max_tiles[slot] = L.max_tiles;
+        ta.tiles[slot] = tiles;
+        tiles_emit_kernel<<<dim3(grid_of(L.max_tiles), 3), 256, 0, s>>>(ta);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "user grouping");
     }
     rc = walk_certify_fallback(ix, p, screen_prec(precision), cascade_of(precision), Uq, n_q, tiles, sorted, ctrl, uflag, flist, uscal,

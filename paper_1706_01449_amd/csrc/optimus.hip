@@ -10,6 +10,7 @@
 // throughput.  Both methods are exact, so the choice changes speed only.
 #include <algorithm>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "../../include/mips.h"
@@ -41,6 +42,22 @@ __global__ void scatter_results(const int* __restrict__ ids, int64_t n, int K,
 
 unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The systematic sample on the device: sample user k < ns is
+// floor((k n_u + off) / ns) (strictly increasing as ns <= n_u).  ids[k]
+// receives sample user k, ids[ns + r] the r-th other user in ascending order.
+// User u has c = ceil((u ns - off) / n_u) sample users below it (clamped to
+// [0, ns]) and is sample user c when floor((c n_u + off) / ns) == u.
+__global__ void sample_ids_kernel(int64_t n_u, int64_t ns, int64_t off, int* ids) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= n_u) return;
+    const int64_t num = u * ns - off;
+    int64_t c = num <= 0 ? 0 : (num + n_u - 1) / n_u;
+    if (c > ns) c = ns;
+    const bool in = c < ns && (c * n_u + off) / ns == u;
+    if (in) ids[c] = (int)u;
+    else ids[ns + (u - c)] = (int)u;
+}
+
 // splitmix64 (Steele, Lea and Flood 2014): seeded stream for the sample.
 uint64_t splitmix(uint64_t& x) {
     uint64_t z = (x += 0x9e3779b97f4a7c15ull);
@@ -49,21 +66,23 @@ uint64_t splitmix(uint64_t& x) {
     return z ^ (z >> 31);
 }
 
-// Stream-ordered device buffers (the runtime's pool makes repeated calls
-// cheap), released on the stream when the scope ends.
+// Device buffers from the library's block cache, released when the scope
+// ends, after the stream has finished with them.
 struct Scratch {
     hipStream_t s;
-    std::vector<void*> p;
+    std::vector<std::pair<void*, size_t>> p;
     explicit Scratch(hipStream_t st) : s(st) {}
     ~Scratch() {
-        for (void* q : p) (void)hipFreeAsync(q, s);
+        (void)hipStreamSynchronize(s);
+        for (auto& q : p) cache_release(q.first, q.second);
     }
     template <typename T>
     hipError_t alloc(T** out, size_t count) {
         void* q = nullptr;
-        hipError_t e = hipMallocAsync(&q, std::max<size_t>(count * sizeof(T), 256), s);
+        size_t got = 0;
+        hipError_t e = cache_alloc(&q, &got, std::max<size_t>(count * sizeof(T), 256));
         if (e == hipSuccess) {
-            p.push_back(q);
+            p.push_back({q, got});
             *out = (T*)q;
         }
         return e;
@@ -119,22 +138,10 @@ extern "C" int mips_optimus_topk(const float* U, int64_t n_u, const float* I, in
     const int64_t kDefaultSample = 131072;
     int64_t ns = sample_users > 0 ? sample_users : std::max<int64_t>(kDefaultSample, n_u / 100);
     ns = std::min(ns, n_u);
-    // systematic sample with a seeded phase: users floor((k + phase) n_u / ns),
-    // k = 0 .. ns-1 (sorted, evenly spread), then the other users in order
-    std::vector<int> perm(n_u);
-    {
-        uint64_t st = seed ^ 0x6f7074696d7573ull;
-        const double phase = (double)(splitmix(st) >> 11) * 0x1p-53;
-        std::vector<unsigned char> in(n_u, 0);
-        for (int64_t k = 0; k < ns; ++k) {
-            const int64_t u = std::min<int64_t>(n_u - 1, (int64_t)(((double)k + phase) * (double)n_u / (double)ns));
-            perm[k] = (int)u;
-            in[u] = 1;
-        }
-        int64_t r = ns;
-        for (int64_t u = 0; u < n_u; ++u)
-            if (!in[u]) perm[r++] = (int)u;
-    }
+    // systematic sample with a seeded offset: users floor((k n_u + off) / ns),
+    // k = 0 .. ns-1 (evenly spread), then the other users in order
+    uint64_t st = seed ^ 0x6f7074696d7573ull;
+    const int64_t off = (int64_t)(splitmix(st) % (uint64_t)n_u);
     const int64_t nr = n_u - ns;
     rep.sample_users = ns;
 
@@ -156,11 +163,10 @@ extern "C" int mips_optimus_topk(const float* U, int64_t n_u, const float* I, in
         TRY(sc.alloc(&ri, (size_t)nr * K), "alloc");
         TRY(sc.alloc(&rs, (size_t)nr * K), "alloc");
     }
-    TRY(hipMemcpyAsync(ids, perm.data(), (size_t)n_u * sizeof(int), hipMemcpyHostToDevice, s), "copy ids");
+    sample_ids_kernel<<<grid1(n_u), 256, 0, s>>>(n_u, ns, off, ids);
     gather_rows_f32<<<grid1(ns * f), 256, 0, s>>>(U, f, ids, ns, Us);
     if (nr > 0) gather_rows_f32<<<grid1(nr * f), 256, 0, s>>>(U, f, ids + ns, nr, Ur);
     TRY(hipGetLastError(), "gather");
-    TRY(hipStreamSynchronize(s), "sync");
 
     // ---- brute force on the sample ------------------------------------------
     const size_t wb = std::max(mips_bmm_topk_workspace_size(ns, n_i, f, K, precision),

@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(64) item_pack_kernel(ItemPrepArgs a) {
     }
     float cm = (item >= 0) ? a.Corig[item] : 0.0f;
     float gm = (item >= 0) ? a.Gorig[item] : 0.0f;
-    if (a.cgpos && h == 0) a.cgpos[p] = make_float2(cm, gm);
+    if (a.cgpos && h == 0) a.cgpos[p] = make_float4(cm, gm, __int_as_float(item), 0.0f);
     for (int off = 16; off >= 1; off >>= 1) {
         cm = fmaxf(cm, __shfl_xor(cm, off));
         gm = fmaxf(gm, __shfl_xor(gm, off));

@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // certification maps positions to items.  The store goes to slot
     // min(count, cap - 1): a list that overflows sends its user to the exact
     // path, whatever its last slot holds.
-    const int lane_slot0 = lane * a.cap;
+    const int lane_slot0 = lane;
     auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 bm, float2 cg)
         __attribute__((always_inline)) {
         const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                     if (hit) {
                         list_insert(L, lb);
                         int2* const cb = a.cand + cand_at(w * UB + ub, 0, 0, a.cap);
-                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1)] =
+                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * kCandStride] =
                             make_int2(__float_as_int(v), ref);
                         cnt[ub] += 1;
                     }
@@ -763,7 +763,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 for (int r = 0; r < 16; ++r) {
                     const int row = 8 * (r >> 2) + 4 * h + (r & 3);
                     if (v[r] >= thr && row < rem) {
-                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1)] =
+                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * kCandStride] =
                             make_int2(__float_as_int(v[r]), b * kTile + row);
                         cnt[ub] += 1;
                     }
@@ -828,7 +828,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 for (int q = 0; q < 8; ++q) {
                     const int j = j0 + q;
                     e[q] = make_int2(0, -1);
-                    if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j : base1 + (j - m0)];
+                    if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * kCandStride : base1 + (j - m0) * kCandStride];
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -837,11 +837,11 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         Ci[q] = (ref >= 0) ? a.Corig[ref] : 0.0f;
                         Gi[q] = (ref >= 0) ? a.Gorig[ref] : 0.0f;
                     } else {
-                        // sorted position: its norms and its item, read together
-                        const float2 cg = (ref >= 0) ? a.cgpos[ref] : make_float2(0.0f, 0.0f);
+                        // sorted position: its norms and its item in one 16-byte read
+                        const float4 cg = (ref >= 0) ? a.cgpos[ref] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                         Ci[q] = cg.x;
                         Gi[q] = cg.y;
-                        e[q].y = (ref >= 0) ? a.perm[ref] : -1;
+                        e[q].y = (ref >= 0) ? __float_as_int(cg.z) : -1;
                     }
                 }
                 int it[8];
