@@ -111,6 +111,14 @@ struct ScreenArgs {
     const float2* cblockmax;  // C x n_blk per-tile maxima in walk order
     const void* qrow;         // n_i x f_pad screen copies by item index
     const int* kexp;          // FP8: row scale exponent by item index
+    // the first wpre tiles of every cluster's list, packed in matrix-core
+    // operand order ([cluster][tile][chunk][lane]) with their per-row (C, G)
+    // and, for E4M3, E8M0 scale bytes ([cluster][tile][row]): a walk tile
+    // below wpre loads without a gather through the list
+    int wpre;
+    const void* wpacked;
+    const float2* wcg;
+    const int* wscale;
     // per-item scalars by item index
     const float* Corig;       // ||i|| rounded up
     const float* Gorig;       // ||i - screen(i)|| + gamma ||screen(i)||, rounded up
@@ -153,6 +161,20 @@ struct FallbackArgs {
     double* out_score;
 };
 
+// Walk prefix tiles of a Maximus index (see ScreenArgs::wpacked).
+struct WalkPackArgs {
+    const int* lists;         // C x n_i_pad walk lists (-1 past the last item)
+    int64_t n_i_pad;
+    int wpre, f_pad, nch;
+    const void* qrow;         // screen copies by item index
+    const int* kexp;          // E4M3 row scale exponents (null otherwise)
+    const float* Corig;
+    const float* Gorig;
+    void* packed;
+    float2* cg;
+    int* scale;
+};
+
 struct ItemPrepArgs {
     const float* I;
     int64_t n_i, n_blk;
@@ -184,6 +206,8 @@ hipError_t launch_item_prep(int prec, const ItemPrepArgs& a, bool pack, hipStrea
 // norms and screen copies of the same items for up to three precisions in
 // one pass (a[p] null: precision p skipped)
 hipError_t launch_item_stats3(const ItemPrepArgs* const (&a)[3], hipStream_t s);
+// walk prefix tiles of C clusters (grid wpre x C)
+hipError_t launch_walk_pack(int prec, const WalkPackArgs& a, int C, hipStream_t s);
 hipError_t launch_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_fp32(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_bf16(const ScreenPlan& p, const ScreenArgs& a, hipStream_t s);

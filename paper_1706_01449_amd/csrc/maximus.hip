@@ -915,6 +915,11 @@ struct mips_maximus_index {
     // bound on the tile count; slots past the last tile hold empty tiles
     int4* tiles[3] = {nullptr, nullptr, nullptr};
     int64_t ntiles[3] = {0, 0, 0};
+    // per screen precision: the first wpre tiles of every list in operand order
+    int wpre[3] = {0, 0, 0};
+    void* wpacked[3] = {nullptr, nullptr, nullptr};
+    float2* wcg[3] = {nullptr, nullptr, nullptr};
+    int* wscale = nullptr;
     // device memory of the index and the build's temporaries (released when
     // the build ends): blocks of the library's cache, with their sizes
     std::vector<std::pair<void*, size_t>> allocs, tmp;
@@ -923,6 +928,9 @@ struct mips_maximus_index {
 namespace {
 
 int ub_slot(int UB) { return UB == 1 ? 0 : (UB == 2 ? 1 : 2); }
+
+// Device memory for the walk prefix tiles of one screen precision.
+constexpr size_t kWalkPrefixBytes = (size_t)16 << 20;
 
 // Device memory of the index and of its build temporaries comes from the
 // library's block cache (a released index leaves its blocks for the next).
@@ -1257,6 +1265,34 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
             item_cg4_kernel<<<grid_of(n_i), 256, 0, s>>>(bm);
             cblockmax_kernel<<<grid_of((int64_t)C * ix->n_blk), 256, 0, s>>>(bm);
             TRY(hipGetLastError(), "tile maxima");
+            // walk prefix tiles: at most kWalkPrefixBytes per precision
+            for (int prec = 0; prec < 3; ++prec) {
+                if (!iap[prec]) continue;
+                const size_t op = prec == PREC_FP32 ? 4 : (prec == PREC_BF16 ? 16 : 32);
+                const size_t tile_bytes = (size_t)iap[prec]->nch * kWave * op;
+                const int64_t fit = (int64_t)(kWalkPrefixBytes / (tile_bytes * (size_t)C));
+                const int wpre = (int)std::min<int64_t>(ix->n_blk, std::max<int64_t>(1, fit));
+                unsigned char* pk = nullptr;
+                TRY(dalloc(ix, &pk, (size_t)C * wpre * tile_bytes), "alloc prefix tiles");
+                TRY(dalloc(ix, &ix->wcg[prec], (size_t)C * wpre * kTile), "alloc");
+                if (prec == PREC_FP8) TRY(dalloc(ix, &ix->wscale, (size_t)C * wpre * kTile), "alloc");
+                ix->wpre[prec] = wpre;
+                ix->wpacked[prec] = pk;
+                WalkPackArgs wa{};
+                wa.lists = ix->lists;
+                wa.n_i_pad = ix->n_i_pad;
+                wa.wpre = wpre;
+                wa.f_pad = iap[prec]->f_pad;
+                wa.nch = iap[prec]->nch;
+                wa.qrow = ix->qrow[prec];
+                wa.kexp = ix->kexp;
+                wa.Corig = ix->Corig[prec];
+                wa.Gorig = ix->Gorig[prec];
+                wa.packed = pk;
+                wa.cg = ix->wcg[prec];
+                wa.scale = prec == PREC_FP8 ? ix->wscale : nullptr;
+                TRY(launch_walk_pack(prec, wa, C, s), "walk prefix tiles");
+            }
         }
     }
 
@@ -1389,6 +1425,10 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
     a.cblockmax = ix->cblockmax[precision];
     a.qrow = ix->qrow[precision];
     a.kexp = ix->kexp;
+    a.wpre = ix->wpre[precision];
+    a.wpacked = ix->wpacked[precision];
+    a.wcg = ix->wcg[precision];
+    a.wscale = ix->wscale;
     a.Corig = ix->Corig[precision];
     a.Gorig = ix->Gorig[precision];
     if (casc && ix->qrow[PREC_BF16]) {

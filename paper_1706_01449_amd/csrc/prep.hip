@@ -311,6 +311,63 @@ __global__ void __launch_bounds__(64) item_pack_kernel(ItemPrepArgs a) {
     if (lane == 0) a.blockmax[b] = make_float2(cm, gm);
 }
 
+// Walk prefix tiles: tile t of cluster c holds list entries t 32 .. t 32 + 31
+// in the layout of item_pack_kernel (one workgroup of 64 lanes per tile).
+template <int PREC>
+__global__ void __launch_bounds__(64) walk_pack_kernel(WalkPackArgs a) {
+    const int t = blockIdx.x, c = blockIdx.y;
+    const int lane = threadIdx.x, m = lane & 31, h = lane >> 5;
+    const int64_t p = (int64_t)t * kTile + m;
+    const int item = a.lists[(int64_t)c * a.n_i_pad + p];
+    const int64_t tile = (int64_t)c * a.wpre + t;
+    const int half = a.f_pad / 2;
+    if (PREC == PREC_BF16) {
+        const uint4* src = (const uint4*)a.qrow;
+        uint4* dst = (uint4*)a.packed;
+        for (int cc = 0; cc < a.nch; ++cc) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (item >= 0) v = src[((int64_t)item * a.f_pad + h * half + cc * 8) / 8];
+            dst[(tile * a.nch + cc) * kWave + lane] = v;
+        }
+    } else if (PREC == PREC_FP8) {
+        const uint4* src = (const uint4*)a.qrow;
+        uint4* dst = (uint4*)a.packed;
+        for (int cc = 0; cc < a.nch; ++cc) {
+            uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+            if (item >= 0) {
+                const int64_t o = ((int64_t)item * a.f_pad + h * half + cc * 32) / 16;
+                v0 = src[o];
+                v1 = src[o + 1];
+            }
+            const int64_t d = ((tile * a.nch + cc) * kWave + lane) * 2;
+            dst[d] = v0;
+            dst[d + 1] = v1;
+        }
+        if (h == 0) a.scale[tile * kTile + m] = (item >= 0 ? a.kexp[item] : 0) + 127;
+    } else {
+        const float* src = (const float*)a.qrow;
+        float* dst = (float*)a.packed;
+        for (int cc = 0; cc < a.nch; ++cc) {
+            float v = 0.0f;
+            if (item >= 0) v = src[(int64_t)item * a.f_pad + h * half + cc];
+            dst[(tile * a.nch + cc) * kWave + lane] = v;
+        }
+    }
+    if (h == 0)
+        a.cg[tile * kTile + m] = item >= 0 ? make_float2(a.Corig[item], a.Gorig[item]) : make_float2(0.0f, 0.0f);
+}
+
+hipError_t launch_walk_pack(int prec, const WalkPackArgs& a, int C, hipStream_t s) {
+    if (a.wpre <= 0) return hipSuccess;
+    const dim3 g((unsigned)a.wpre, (unsigned)C);
+    switch (prec) {
+        case PREC_FP32: walk_pack_kernel<PREC_FP32><<<g, 64, 0, s>>>(a); break;
+        case PREC_BF16: walk_pack_kernel<PREC_BF16><<<g, 64, 0, s>>>(a); break;
+        default: walk_pack_kernel<PREC_FP8><<<g, 64, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
 __global__ void nonfinite_scan_kernel(const float* U, int64_t nu, const float* I, int64_t ni,
                                       Ctrl* ctrl) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

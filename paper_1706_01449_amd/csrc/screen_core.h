@@ -442,15 +442,24 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             if (PREC == PREC_FP8) iscale = a.pscale[p];
         } else {
             item = clist[p];                        // -1 past the last item
-            const int64_t row = item >= 0 ? item : 0;
-            if constexpr (pair_bound_walk(WALK, PREC, KM, NCH))
-                cg = make_float2(a.Corig[row], a.Gorig[row]);   // for the per-pair bound
+            if (b < a.wpre) {
+                // a prefix tile: operands already in matrix-core order
+                const int64_t tl = (int64_t)cluster * a.wpre + b;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                ai[c] = P::load_row(a.qrow, row, a.f_pad, h * half + c * E);
-                if (item < 0) ai[c] = P::zero();
+                for (int c = 0; c < NCH; ++c) ai[c] = P::load_packed(a.wpacked, tl, c, NCH, lane);
+                if constexpr (pair_bound_walk(WALK, PREC, KM, NCH)) cg = a.wcg[tl * kTile + n];
+                if (PREC == PREC_FP8) iscale = a.wscale[tl * kTile + n];
+            } else {
+                const int64_t row = item >= 0 ? item : 0;
+                if constexpr (pair_bound_walk(WALK, PREC, KM, NCH))
+                    cg = make_float2(a.Corig[row], a.Gorig[row]);   // for the per-pair bound
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    ai[c] = P::load_row(a.qrow, row, a.f_pad, h * half + c * E);
+                    if (item < 0) ai[c] = P::zero();
+                }
+                if (PREC == PREC_FP8) iscale = (item >= 0) ? a.kexp[item] + 127 : 127;
             }
-            if (PREC == PREC_FP8) iscale = (item >= 0) ? a.kexp[item] + 127 : 127;
         }
     };
 
