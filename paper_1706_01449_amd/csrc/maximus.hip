@@ -120,11 +120,19 @@ struct AssignArgs {
     int lds_theta;             // final pass: per-workgroup theta maxima in LDS
     const float* img;          // ntile * ks * 64 floats
     int* assign;
-    // final pass (index build): theta_b of every cluster from its members
+    // angle passes: the index build's final pass takes theta_b of every
+    // cluster from its members; a vector query tests each vector's cover
     const double* chat;        // unit centroids, C x f (zero rows for zero centroids)
     const double* cnorm;       // ||c|| in float64
     unsigned long long* theta_bits;
+    const double* theta;       // cover test: theta_b
+    int* uflag;                // cover test: 1 for a vector sent to the exact path
+    int* flist;
+    Ctrl* ctrl;
 };
+
+// Passes of the assignment kernel.
+constexpr int kAssignPlain = 0, kAssignTheta = 1, kAssignCover = 2;
 
 constexpr int kAssignWaves = 4;
 constexpr int kAssignLds = 65536;      // dynamic LDS budget of the assignment kernel
@@ -141,8 +149,9 @@ inline int assign_chunk_tiles(int f, int C, bool final_pass) {
     return std::max(1, std::min(ntile, fit));
 }
 
-template <int KS, bool FINAL>
+template <int KS, int MODE>
 __global__ void __launch_bounds__(256) assign_mfma_kernel(AssignArgs a) {
+    constexpr bool FINAL = MODE == kAssignTheta;
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
     const int f = a.f, ks = a.ks, ksp = ks >> 1;
@@ -224,22 +233,28 @@ __global__ void __launch_bounds__(256) assign_mfma_kernel(AssignArgs a) {
             const int oi = xor32_i(besti);
             if (ov > bestv || (ov == bestv && oi < besti)) { bestv = ov; besti = oi; }
         }
-        if (h == 0 && valid) a.assign[u0 + n] = besti;
-        if constexpr (FINAL) {
+        if (MODE != kAssignCover && h == 0 && valid) a.assign[u0 + n] = besti;
+        if constexpr (MODE != kAssignPlain) {
             // angle between the user and its centroid in float64 (Kahan:
             // 2 atan2(|u^ - c^|, |u^ + c^|)); lane half h sums the
             // coordinates j with (j / 2) % 2 == h, so the two halves read
             // neighbouring pairs of the unit centroid
             double n2 = 0.0;
+            bool fin = true;
             for (int j = 2 * h; j < f; j += 4) {
-                const double x0 = valid ? (double)uval(j) : 0.0;
+                const float v0 = valid ? uval(j) : 0.0f;
+                fin = fin && __builtin_isfinite(v0);
+                const double x0 = (double)v0;
                 n2 = fma(x0, x0, n2);
                 if (j + 1 < f) {
-                    const double x1 = valid ? (double)uval(j + 1) : 0.0;
+                    const float v1 = valid ? uval(j + 1) : 0.0f;
+                    fin = fin && __builtin_isfinite(v1);
+                    const double x1 = (double)v1;
                     n2 = fma(x1, x1, n2);
                 }
             }
             n2 += xor32_d(n2);
+            fin = fin && xor32_i((int)fin) != 0;
             const double nc = a.cnorm[besti];
             const bool use = valid && n2 > 0.0 && nc > 0.0;
             double d = 0.0, s = 0.0;
@@ -270,11 +285,31 @@ __global__ void __launch_bounds__(256) assign_mfma_kernel(AssignArgs a) {
             }
             d += xor32_d(d);
             s += xor32_d(s);
-            if (use && h == 0) {
-                const double th = 2.0 * atan2(sqrt(d), sqrt(s));
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(th);
-                if (a.lds_theta) atomicMax(&lt[besti], bits);
-                else atomicMax(&a.theta_bits[besti], bits);
+            if constexpr (MODE == kAssignTheta) {
+                if (use && h == 0) {
+                    const double th = 2.0 * atan2(sqrt(d), sqrt(s));
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(th);
+                    if (a.lds_theta) atomicMax(&lt[besti], bits);
+                    else atomicMax(&a.theta_bits[besti], bits);
+                }
+            } else {
+                // a vector may walk its nearest cluster's list when its angle to
+                // the centroid is at most theta_b (a zero centroid has theta_b =
+                // pi); the others, zero and non-finite rows take the exact path
+                if (h == 0 && valid) {
+                    bool cov = fin && n2 > 0.0;
+                    if (cov && nc > 0.0) cov = 2.0 * atan2(sqrt(d), sqrt(s)) <= a.theta[besti];
+                    const int64_t q = u0 + n;
+                    if (!fin) atomicOr(&a.ctrl->nonfinite, 1u);
+                    if (cov) {
+                        a.assign[q] = besti;
+                    } else {
+                        a.assign[q] = -1;                 // left out of the grouping
+                        a.uflag[q] = 1;
+                        const unsigned int k = atomicAdd(&a.ctrl->fb_count, 1u);
+                        a.flist[k] = (int)q;
+                    }
+                }
             }
         }
     }
@@ -962,7 +997,9 @@ void free_index(mips_maximus_index* ix) {
 // Nearest centroid of n_u user rows (float32 MFMA); the final pass of the
 // build also takes theta_b into theta_bits.
 hipError_t launch_assign(const mips_maximus_index* ix, const float* U, int64_t n_u, int* assign,
-                         bool final_pass, unsigned long long* theta_bits, hipStream_t s) {
+                         int mode, unsigned long long* theta_bits, int* uflag, int* flist, Ctrl* ctrl,
+                         hipStream_t s) {
+    const bool final_pass = mode == kAssignTheta;
     AssignArgs a{};
     a.U = U;
     a.n_u = n_u;
@@ -978,14 +1015,19 @@ hipError_t launch_assign(const mips_maximus_index* ix, const float* U, int64_t n
     a.chat = ix->chat;
     a.cnorm = ix->cnorm;
     a.theta_bits = theta_bits;
+    a.theta = ix->theta;
+    a.uflag = uflag;
+    a.flist = flist;
+    a.ctrl = ctrl;
     const size_t lds = assign_theta_bytes(ix->C, final_pass) + (size_t)a.chunk_tiles * a.ks * 256 +
                        assign_stage_bytes(ix->f);
     const int64_t n_ublk = (n_u + 31) / 32;
     const unsigned grid = (unsigned)std::min<int64_t>((n_ublk + kAssignWaves - 1) / kAssignWaves, 1024);
-#define ASSIGN_LAUNCH(KS)                                                          \
-    do {                                                                           \
-        if (final_pass) assign_mfma_kernel<KS, true><<<grid, 256, lds, s>>>(a);    \
-        else assign_mfma_kernel<KS, false><<<grid, 256, lds, s>>>(a);              \
+#define ASSIGN_LAUNCH(KS)                                                                   \
+    do {                                                                                    \
+        if (mode == kAssignTheta) assign_mfma_kernel<KS, kAssignTheta><<<grid, 256, lds, s>>>(a); \
+        else if (mode == kAssignCover) assign_mfma_kernel<KS, kAssignCover><<<grid, 256, lds, s>>>(a); \
+        else assign_mfma_kernel<KS, kAssignPlain><<<grid, 256, lds, s>>>(a);                \
     } while (0)
     if (a.ks <= 16) ASSIGN_LAUNCH(16);
     else if (a.ks <= 32) ASSIGN_LAUNCH(32);
@@ -996,66 +1038,6 @@ hipError_t launch_assign(const mips_maximus_index* ix, const float* U, int64_t n
 }
 
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// Queries for arbitrary user vectors (new users, or any subset).  A vector
-// may use cluster c's list when its angle to the centroid is at most
-// theta_b[c]: the bound of Eq. (appx_bound) only needs theta_uc <= theta_b
-// (Section III-C), so such a vector is covered exactly like a member.  Each
-// vector tries its nearest centroid; the others take the exact path.
-// ---------------------------------------------------------------------------
-__global__ void qcover_kernel(const float* __restrict__ Uq, int64_t n_q, int f,
-                              int* __restrict__ qassign, const double* __restrict__ chat,
-                              const double* __restrict__ cnorm, const double* __restrict__ theta,
-                              int* uflag, int* flist, Ctrl* ctrl) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n_q) return;
-    const float* row = Uq + q * f;
-    // the sums of the build's final assignment pass, in the same order (the
-    // coordinates j with (j / 2) % 2 == 0 and those with (j / 2) % 2 == 1
-    // summed apart, each in ascending j, then added), so an indexed user
-    // queried as a vector measures the same angle
-    double n2a = 0.0, n2b = 0.0;
-    bool finite = true;
-    for (int j = 0; j < f; ++j) {
-        const double x = (double)row[j];
-        finite = finite && __builtin_isfinite(row[j]);
-        if (((j >> 1) & 1) == 0) n2a = fma(x, x, n2a);
-        else n2b = fma(x, x, n2b);
-    }
-    const double n2 = n2a + n2b;
-    const int c = qassign[q];
-    bool covered = false;
-    if (finite && n2 > 0.0) {
-        if (!(cnorm[c] > 0.0)) {
-            covered = true;                       // theta_b = pi: the bound is ||i||
-        } else {
-            // Kahan's angle on the unit vectors, as for theta_b
-            const double rinv = 1.0 / sqrt(n2);
-            const double* y = chat + (int64_t)c * f;
-            double da = 0.0, sa = 0.0, db = 0.0, sb = 0.0;
-            for (int j = 0; j < f; ++j) {
-                const double x = (double)row[j] * rinv;
-                const double p = x - y[j], r = x + y[j];
-                if (((j >> 1) & 1) == 0) {
-                    da = fma(p, p, da);
-                    sa = fma(r, r, sa);
-                } else {
-                    db = fma(p, p, db);
-                    sb = fma(r, r, sb);
-                }
-            }
-            covered = 2.0 * atan2(sqrt(da + db), sqrt(sa + sb)) <= theta[c];
-        }
-    }
-    if (!finite) atomicOr(&ctrl->nonfinite, 1u);
-    if (!covered) {
-        qassign[q] = -1;                          // left out of the grouping
-        uflag[q] = 1;
-        const unsigned int k = atomicAdd(&ctrl->fb_count, 1u);
-        flist[k] = (int)q;
-    }
-}
 
 extern "C" {
 
@@ -1139,7 +1121,8 @@ int mips_maximus_build(const float* U, int64_t n_u, const float* I, int64_t n_i,
         cent_prep_kernel<<<ntile, 256, f <= 254 ? (size_t)32 * f * 8 : 0, s>>>(
             ix->cent, C, f, ks, ix->img, ix->cnorm, ix->chat, counts, last ? ix->theta : nullptr);
         // the final assignment also gives theta_b (Algorithm 1, ConstructIndex)
-        TRY(launch_assign(ix, ix->U, n_u, ix->assign, last, (unsigned long long*)ix->theta, s), "assignment");
+        TRY(launch_assign(ix, ix->U, n_u, ix->assign, last ? kAssignTheta : kAssignPlain,
+                          (unsigned long long*)ix->theta, nullptr, nullptr, nullptr, s), "assignment");
         if (last) break;
         kmeans_sum_kernel<<<dim3(sum_gx, nsl), 256, sum_lds, s>>>(ix->U, n_u, f, ix->assign, absmax, rows,
                                                                  cs, sums, counts, C);
@@ -1569,6 +1552,13 @@ int mips_maximus_query(const mips_maximus_index* ix, int32_t K, int32_t precisio
     return MIPS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Queries for arbitrary user vectors (new users, or any subset).  A vector
+// may use cluster c's list when its angle to the centroid is at most
+// theta_b[c]: the bound of Eq. (appx_bound) only needs theta_uc <= theta_b
+// (Section III-C), so such a vector is covered exactly like a member.  Each
+// vector tries its nearest centroid; the others take the exact path.
+// ---------------------------------------------------------------------------
 size_t mips_maximus_query_users_workspace_size(const mips_maximus_index* ix, int64_t n_q,
                                                int32_t K, int32_t precision) {
     if (!ix || n_q < 1 || n_q >= ((int64_t)1 << 31) || K < 1 || (int64_t)K > ix->n_i ||
@@ -1612,11 +1602,10 @@ int mips_maximus_query_users(const mips_maximus_index* ix, const float* Uq, int6
     if ((e = launch_zero(ws, L.zero_end, s)) != hipSuccess) return hip_fail(e, "zero");
     if (p.fast) {
         PhaseTimer t(MIPS_PHASE_WALK, s);
-        const int C = ix->C, f = ix->f;
-        if ((e = launch_assign(ix, Uq, n_q, qassign, false, nullptr, s)) != hipSuccess)
+        const int C = ix->C;
+        // nearest cluster and its cover test in one pass
+        if ((e = launch_assign(ix, Uq, n_q, qassign, kAssignCover, nullptr, uflag, flist, ctrl, s)) != hipSuccess)
             return hip_fail(e, "assignment");
-        qcover_kernel<<<grid_of(n_q), 256, 0, s>>>(Uq, n_q, f, qassign, ix->chat, ix->cnorm, ix->theta,
-                                                   uflag, flist, ctrl);
         // covered vectors grouped by cluster (stable), then their walk tiles
         group_count_kernel<<<L.nch, 256, 0, s>>>(qassign, n_q, C, L.nch, ccounts);
         group_scan_kernel<<<C, 64, 0, s>>>(ccounts, L.nch, ccount);
