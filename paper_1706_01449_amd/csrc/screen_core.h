@@ -273,7 +273,13 @@ __host__ __device__ constexpr bool fused_certify(int prec, int km, int ub) {
 constexpr int kSweepBrute = 0, kSweepPruned = 1, kSweepWalk = 2;
 
 template <int PREC, int KM, int NCH, int UB, int MODE>
-__global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
+// bmax_base: a.blockmax (brute force, norm-pruned) or a.cblockmax (walk), as
+// a separate restrict-qualified argument: the compiler can then prove that no
+// store of the kernel reaches it and reads the per-tile maxima with scalar
+// loads (through the struct it issues vector loads, whose waits would also
+// drain the operand loads in flight).
+__global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
+                                                    const float2* __restrict__ bmax_base) {
     constexpr bool WALK = MODE == kSweepWalk;
     typedef Prec<PREC> P;
     typedef typename P::Op Op;
@@ -322,17 +328,49 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     bool act[UB];
 
     // ---- prologue: load, quantise and measure this wave's users ----------
+    // Brute force and norm-pruned sweep with lists in LDS: the 32 users of a
+    // block are consecutive rows of U, so the wave copies the block's rows
+    // into the list array with coalesced loads, all issued together (one
+    // memory latency per block; one row per lane would take one per factor
+    // batch), and each lane reads its user's factors from LDS.  The lists
+    // are first written after the prologue.
+    constexpr int kStageMax = 2 * kTile * NCH * E;    // floats of 32 rows at f = f_pad
+    constexpr bool kStage = !WALK && LDSL && UB * KM * kWave >= kStageMax;
+    constexpr int kStageIt = (kStageMax + kWave - 1) / kWave;
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
         bool valid;
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
         const float* urow = a.U + u * a.f;
+        if constexpr (kStage) {
+            const int64_t u0 = (w * UB + ub) * kTile;
+            const int64_t left = a.n_u - u0;
+            const int nf = (int)(left <= 0 ? 0 : (left < kTile ? left : kTile)) * a.f;
+            const float* src = a.U + u0 * a.f;
+            float v[kStageIt];
+#pragma unroll
+            for (int t = 0; t < kStageIt; ++t) {
+                const int i = lane + t * kWave;
+                v[t] = (i < nf) ? src[i] : 0.0f;
+            }
+            __syncthreads();                          // the previous block's reads are done
+#pragma unroll
+            for (int t = 0; t < kStageIt; ++t) {
+                const int i = lane + t * kWave;
+                if (i < nf) s_lst[i] = v[t];
+            }
+            __syncthreads();
+        }
+        auto ux = [&](int j) __attribute__((always_inline)) -> float {
+            if constexpr (kStage) return s_lst[n * a.f + j];   // the staged copy
+            else return urow[j];
+        };
         double s2 = 0.0, r2 = 0.0, q2 = 0.0;
         float amax = 0.0f;
         bool finite = true;
         if (valid) {
             for (int j = h * half; j < h * half + half && j < a.f; ++j) {
-                const float x = urow[j];
+                const float x = ux(j);
                 finite = finite && ((__float_as_uint(x) & 0x7f800000u) != 0x7f800000u);
                 s2 += (double)x * (double)x;
                 amax = fmaxf(amax, fabsf(x));
@@ -350,14 +388,14 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
             if (valid) {
                 const int j0 = h * half + c * E;
                 if constexpr (PREC == PREC_FP32) {
-                    const float x = (j0 < a.f) ? urow[j0] : 0.0f;
+                    const float x = (j0 < a.f) ? ux(j0) : 0.0f;
                     op = __builtin_bit_cast(Op, x);
                 } else if constexpr (PREC == PREC_BF16) {
                     uint32_t wd[4];
 #pragma unroll
                     for (int e = 0; e < 8; e += 2) {
-                        const float x0 = (j0 + e < a.f) ? urow[j0 + e] : 0.0f;
-                        const float x1 = (j0 + e + 1 < a.f) ? urow[j0 + e + 1] : 0.0f;
+                        const float x0 = (j0 + e < a.f) ? ux(j0 + e) : 0.0f;
+                        const float x1 = (j0 + e + 1 < a.f) ? ux(j0 + e + 1) : 0.0f;
                         const uint16_t b0 = f32_to_bf16_bits(x0), b1 = f32_to_bf16_bits(x1);
                         const double d0 = bf16_bits_to_f32(b0), d1 = bf16_bits_to_f32(b1);
                         r2 += ((double)x0 - d0) * ((double)x0 - d0) + ((double)x1 - d1) * ((double)x1 - d1);
@@ -372,7 +410,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                         uint32_t word = 0;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const float x = (j0 + e + q < a.f) ? urow[j0 + e + q] : 0.0f;
+                            const float x = (j0 + e + q < a.f) ? ux(j0 + e + q) : 0.0f;
                             const uint32_t byte = e4m3_encode(__builtin_ldexpf(x, -k));
                             const double d = __builtin_ldexp((double)e4m3_decode(byte), k);
                             r2 += ((double)x - d) * ((double)x - d);
@@ -425,15 +463,14 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     const bool k_is_km = a.K == KM;
     const int n_blk = (int)a.n_blk;   // < 2^26 (n_i < 2^31): 32-bit scalar tile arithmetic
     const int* clist = WALK ? a.lists + (int64_t)cluster * a.n_i_pad : nullptr;
-    // per-tile bound maxima (prefetched with the tile operands)
-    const float2* bmax = WALK ? a.cblockmax + (int64_t)cluster * n_blk : a.blockmax;
+    // per-tile bound maxima (max C_i, max G_i over the tile's items)
+    const float2* bmax = WALK ? bmax_base + (int64_t)cluster * n_blk : bmax_base;
 
     // This lane's A-operand chunks of tile b (row n), the row's item index
     // (-1 past the end) and, for E4M3, the row's E8M0 scale byte.
-    auto load_tile = [&](int b, Op (&ai)[NCH], int& item, int& iscale, float2& bm, float2& cg)
+    auto load_tile = [&](int b, Op (&ai)[NCH], int& item, int& iscale, float2& cg)
         __attribute__((always_inline)) {
         const int64_t p = (int64_t)b * kTile + n;
-        bm = bmax[b];
         if constexpr (!WALK) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
@@ -501,9 +538,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         for (int b = 0; b < W; ++b) {
             Op ai[NCH];
             int it = -1, sc = 127;
-            float2 bmw;
             float2 cgw;
-            load_tile(b, ai, it, sc, bmw, cgw);
+            load_tile(b, ai, it, sc, cgw);
+            const float2 bmw = bmax[b];
 #pragma unroll
             for (int ub = 0; ub < UB; ++ub) {
                 floatx16_t acc = score_one(b, ai, sc, ub);
@@ -540,9 +577,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 if (b < n_blk) {
                     Op ai[NCH];
                     int it = -1, sc = 127;
-                    float2 bmw;
                     float2 cgw;
-                    load_tile(b, ai, it, sc, bmw, cgw);
+                    load_tile(b, ai, it, sc, cgw);
                     floatx16_t acc = score_one(b, ai, sc, ub);
                     mask_rows(b, acc);
 #pragma unroll
@@ -573,8 +609,13 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
     // min(count, cap - 1): a list that overflows sends its user to the exact
     // path, whatever its last slot holds.
     const int lane_slot0 = lane;
-    auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 bm, float2 cg)
+    auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 cg)
         __attribute__((always_inline)) {
+        // the tile's bound maxima, read (scalar load) where they are used: a
+        // vector load issued with the tile's operands was carried to the
+        // next iteration by a copy at the loop's back edge, and the wait for
+        // that copy also drained the operand loads issued after it
+        const float2 bm = bmax[b];
         const float ee = fmaf(Au[ub], bm.x, fmaf(Bu[ub], bm.y, slk[ub]));
         const float thr = tauf[ub] - ee;
         // maxima of the four row groups {4g .. 4g+3}, then of the tile
@@ -686,18 +727,18 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         const int last = n_blk - 1;
         Op ops[2][NCH];
         int itm[2] = {-1, -1}, scl[2] = {127, 127};
-        float2 bmx[2], cgx[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
+        float2 cgx[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
         floatx16_t acc[2];
         int itP = -1;                 // the previous tile's item, bound and norms
-        float2 bmP = make_float2(0.0f, 0.0f), cgP = make_float2(0.0f, 0.0f);
-        load_tile(b0, ops[0], itm[0], scl[0], bmx[0], cgx[0]);
-        load_tile(b0 + 1 < n_blk ? b0 + 1 : b0, ops[1], itm[1], scl[1], bmx[1], cgx[1]);
+        float2 cgP = make_float2(0.0f, 0.0f);
+        load_tile(b0, ops[0], itm[0], scl[0], cgx[0]);
+        load_tile(b0 + 1 < n_blk ? b0 + 1 : b0, ops[1], itm[1], scl[1], cgx[1]);
         // tile b from operand set T (= b mod 2); false: every user stopped
         // after tile b - 1 (tile b's products are then unused)
         auto sweep = [&](int b, auto tconst) __attribute__((always_inline)) -> bool {
             constexpr int T = decltype(tconst)::value;
             const int itC = itm[T], scC = scl[T];
-            const float2 bmC = bmx[T], cgC = cgx[T];
+            const float2 cgC = cgx[T];
             if constexpr (UB <= 2) {
                 // all products of the tile (independent chains, interleaved
                 // by the compiler), then the tests and the stop test
@@ -710,27 +751,26 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
                 // on 480,000 x 17,770; for the bfloat16 screen at f = 100 the
                 // free schedule was faster)
                 if constexpr (PREC == PREC_FP32) __builtin_amdgcn_sched_barrier(0);
-                load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
+                load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], cgx[T]);
 #pragma unroll
-                for (int j = 0; j < UB; ++j) test_block(b, j, acc[j], itC, bmC, cgC);
+                for (int j = 0; j < UB; ++j) test_block(b, j, acc[j], itC, cgC);
                 return stop_after(b);
             } else {
 #pragma unroll
                 for (int j = 0; j < UB; ++j) {
                     acc[(T * UB + j) & 1] = score_one(b, ops[T], scC, j);
                     if (j == UB - 1)
-                        load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], bmx[T], cgx[T]);
+                        load_tile(b + 2 < last ? b + 2 : last, ops[T], itm[T], scl[T], cgx[T]);
                     if (j == 0) {
                         if (b > b0) {
-                            test_block(b - 1, UB - 1, acc[(T * UB + 1) & 1], itP, bmP, cgP);
+                            test_block(b - 1, UB - 1, acc[(T * UB + 1) & 1], itP, cgP);
                             if (!stop_after(b - 1)) return false;
                         }
                     } else {
-                        test_block(b, j - 1, acc[(T * UB + j - 1) & 1], itC, bmC, cgC);
+                        test_block(b, j - 1, acc[(T * UB + j - 1) & 1], itC, cgC);
                     }
                 }
                 itP = itC;
-                bmP = bmC;
                 cgP = cgC;
                 return true;
             }
@@ -738,15 +778,30 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         // a false sweep: every user stopped after tile b (two blocks or
         // fewer) or after tile b - 1 (rotated blocks)
         constexpr int kStopLag = UB <= 2 ? 1 : 0;
-        for (int b = b0; b < n_blk; b += 2) {
-            if (!sweep(b, std::integral_constant<int, 0>{})) { b_done = b + kStopLag; break; }
-            if (b + 1 >= n_blk) break;
-            if (!sweep(b + 1, std::integral_constant<int, 1>{})) { b_done = b + 1 + kStopLag; break; }
+        if constexpr (MODE == kSweepBrute && UB > 2) {
+            // No stop test: the loop runs while both tiles of a pair exist
+            // and an odd last tile is swept after it.  An exit between the
+            // halves would give the wait-count analysis a path on which the
+            // first half's operand loads are the newest at the loop head,
+            // which then waits for every load in flight (the two-tile
+            // prefetch lost on every other tile).
+            int b = b0;
+            for (; b + 1 < n_blk; b += 2) {
+                sweep(b, std::integral_constant<int, 0>{});
+                sweep(b + 1, std::integral_constant<int, 1>{});
+            }
+            if (b < n_blk) sweep(b, std::integral_constant<int, 0>{});
+        } else {
+            for (int b = b0; b < n_blk; b += 2) {
+                if (!sweep(b, std::integral_constant<int, 0>{})) { b_done = b + kStopLag; break; }
+                if (b + 1 >= n_blk) break;
+                if (!sweep(b + 1, std::integral_constant<int, 1>{})) { b_done = b + 1 + kStopLag; break; }
+            }
         }
         if (UB > 2 && b_done == n_blk) {
             // the last block of the last tile (accumulator ((last - b0) UB + UB - 1) mod 2)
-            if (((last - b0) & 1) == 0) test_block(last, UB - 1, acc[(UB - 1) & 1], itP, bmP, cgP);
-            else test_block(last, UB - 1, acc[(2 * UB - 1) & 1], itP, bmP, cgP);
+            if (((last - b0) & 1) == 0) test_block(last, UB - 1, acc[(UB - 1) & 1], itP, cgP);
+            else test_block(last, UB - 1, acc[(2 * UB - 1) & 1], itP, cgP);
         }
     }
 
@@ -755,9 +810,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a) {
         for (int b = 0; b < W; ++b) {
             Op ai[NCH];
             int it = -1, sc = 127;
-            float2 bm;
             float2 cgw;
-            load_tile(b, ai, it, sc, bm, cgw);
+            load_tile(b, ai, it, sc, cgw);
+            const float2 bm = bmax[b];
             const int rem = (int)(a.n_i - (int64_t)b * kTile);   // rows holding items
 #pragma unroll
             for (int ub = 0; ub < UB; ++ub) {
@@ -978,13 +1033,13 @@ static hipError_t go_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_
     const dim3 grid((unsigned)p.n_waves), blk(64);
     if (a.walk) {
         if (p.UB != UBS) return hipErrorInvalidValue;   // plan and kernel disagree
-        screen_kernel<PREC, KM, NCH, UBS, kSweepWalk><<<grid, blk, 0, s>>>(a);
+        screen_kernel<PREC, KM, NCH, UBS, kSweepWalk><<<grid, blk, 0, s>>>(a, a.cblockmax);
     } else if (a.prune) {
         if (p.UB != UBS) return hipErrorInvalidValue;
-        screen_kernel<PREC, KM, NCH, UBS, kSweepPruned><<<grid, blk, 0, s>>>(a);
+        screen_kernel<PREC, KM, NCH, UBS, kSweepPruned><<<grid, blk, 0, s>>>(a, a.blockmax);
     } else {
         if (p.UB != UBB) return hipErrorInvalidValue;
-        screen_kernel<PREC, KM, NCH, UBB, kSweepBrute><<<grid, blk, 0, s>>>(a);
+        screen_kernel<PREC, KM, NCH, UBB, kSweepBrute><<<grid, blk, 0, s>>>(a, a.blockmax);
     }
     return hipGetLastError();
 }
