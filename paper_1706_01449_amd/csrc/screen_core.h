@@ -328,41 +328,65 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
     bool act[UB];
 
     // ---- prologue: load, quantise and measure this wave's users ----------
-    // Brute force and norm-pruned sweep with lists in LDS: the 32 users of a
-    // block are consecutive rows of U, so the wave copies the block's rows
-    // into the list array with coalesced loads, all issued together (one
-    // memory latency per block; one row per lane would take one per factor
-    // batch), and each lane reads its user's factors from LDS.  The lists
-    // are first written after the prologue.
+    // The 32 user rows of a block are first copied to LDS with all their
+    // loads issued together (one memory latency per block; one row per lane
+    // would take one per factor batch), and each lane reads its user's
+    // factors from there.  Brute force and norm-pruned sweep: the rows are
+    // consecutive in U (one coalesced copy) and the copy goes to the K-list
+    // array where that is in LDS and large enough (the lists are first
+    // written after the prologue); walk: gathered, lane j loading factor j
+    // of each row, into an LDS buffer of its own (f_pad <= 64).  A buffer
+    // of its own for the float32 brute force was measured slower (8.45 vs
+    // 8.52 ms on 480,000 x 17,770), so there each lane reads its own row.
     constexpr int kStageMax = 2 * kTile * NCH * E;    // floats of 32 rows at f = f_pad
-    constexpr bool kStage = !WALK && LDSL && UB * KM * kWave >= kStageMax;
+    constexpr bool kStageL = !WALK && LDSL && UB * KM * kWave >= kStageMax;
+    constexpr bool kStageS = WALK && PREC != PREC_FP8 && kStageMax <= kTile * kWave;
+    constexpr bool kStage = kStageL || kStageS;
     constexpr int kStageIt = (kStageMax + kWave - 1) / kWave;
+    __shared__ float s_stage[kStageS ? kStageMax : 1];
+    float* const stage = kStageL ? s_lst : s_stage;
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
         bool valid;
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
         const float* urow = a.U + u * a.f;
         if constexpr (kStage) {
-            const int64_t u0 = (w * UB + ub) * kTile;
-            const int64_t left = a.n_u - u0;
-            const int nf = (int)(left <= 0 ? 0 : (left < kTile ? left : kTile)) * a.f;
-            const float* src = a.U + u0 * a.f;
-            float v[kStageIt];
+            constexpr int kVn = WALK ? kTile : kStageIt;   // walk: one value per row
+            float v[kVn];
+            if constexpr (!WALK) {
+                const int64_t u0 = (w * UB + ub) * kTile;
+                const int64_t left = a.n_u - u0;
+                const int nf = (int)(left <= 0 ? 0 : (left < kTile ? left : kTile)) * a.f;
+                const float* src = a.U + u0 * a.f;
 #pragma unroll
-            for (int t = 0; t < kStageIt; ++t) {
-                const int i = lane + t * kWave;
-                v[t] = (i < nf) ? src[i] : 0.0f;
+                for (int t = 0; t < kStageIt; ++t) {
+                    const int i = lane + t * kWave;
+                    v[t] = (i < nf) ? src[i] : 0.0f;
+                }
+            } else {
+                // f <= f_pad <= 64: lane j holds factor j of row t
+                const int rows = tile.z - ub * kTile;     // users of this block (may be <= 0)
+                const int mine = (lane < rows && lane < kTile) ? a.sorted_users[tile.y + ub * kTile + lane] : 0;
+#pragma unroll
+                for (int t = 0; t < kTile; ++t) {
+                    const int ut = __builtin_amdgcn_readlane(mine, t);
+                    v[t] = (t < rows && lane < a.f) ? a.U[(int64_t)ut * a.f + lane] : 0.0f;
+                }
             }
             __syncthreads();                          // the previous block's reads are done
 #pragma unroll
-            for (int t = 0; t < kStageIt; ++t) {
-                const int i = lane + t * kWave;
-                if (i < nf) s_lst[i] = v[t];
+            for (int t = 0; t < kVn; ++t) {
+                if constexpr (!WALK) {
+                    const int i = lane + t * kWave;
+                    if (i < kTile * a.f) stage[i] = v[t];
+                } else {
+                    if (lane < a.f) stage[t * a.f + lane] = v[t];
+                }
             }
             __syncthreads();
         }
         auto ux = [&](int j) __attribute__((always_inline)) -> float {
-            if constexpr (kStage) return s_lst[n * a.f + j];   // the staged copy
+            if constexpr (kStage) return stage[n * a.f + j];   // the staged copy
             else return urow[j];
         };
         double s2 = 0.0, r2 = 0.0, q2 = 0.0;
