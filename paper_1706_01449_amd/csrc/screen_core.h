@@ -350,39 +350,38 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
         bool valid;
         const int64_t u = user_of(a, UB, w, ub, n, tile, &valid);
         const float* urow = a.U + u * a.f;
-        if constexpr (kStage) {
-            constexpr int kVn = WALK ? kTile : kStageIt;   // walk: one value per row
-            float v[kVn];
-            if constexpr (!WALK) {
-                const int64_t u0 = (w * UB + ub) * kTile;
-                const int64_t left = a.n_u - u0;
-                const int nf = (int)(left <= 0 ? 0 : (left < kTile ? left : kTile)) * a.f;
-                const float* src = a.U + u0 * a.f;
+        if constexpr (kStage && !WALK) {
+            const int64_t u0 = (w * UB + ub) * kTile;
+            const int64_t left = a.n_u - u0;
+            const int nf = (int)(left <= 0 ? 0 : (left < kTile ? left : kTile)) * a.f;
+            const float* src = a.U + u0 * a.f;
+            float v[kStageIt];
 #pragma unroll
-                for (int t = 0; t < kStageIt; ++t) {
-                    const int i = lane + t * kWave;
-                    v[t] = (i < nf) ? src[i] : 0.0f;
-                }
-            } else {
-                // f <= f_pad <= 64: lane j holds factor j of row t
-                const int rows = tile.z - ub * kTile;     // users of this block (may be <= 0)
-                const int mine = (lane < rows && lane < kTile) ? a.sorted_users[tile.y + ub * kTile + lane] : 0;
-#pragma unroll
-                for (int t = 0; t < kTile; ++t) {
-                    const int ut = __builtin_amdgcn_readlane(mine, t);
-                    v[t] = (t < rows && lane < a.f) ? a.U[(int64_t)ut * a.f + lane] : 0.0f;
-                }
+            for (int t = 0; t < kStageIt; ++t) {
+                const int i = lane + t * kWave;
+                v[t] = (i < nf) ? src[i] : 0.0f;
             }
             __syncthreads();                          // the previous block's reads are done
 #pragma unroll
-            for (int t = 0; t < kVn; ++t) {
-                if constexpr (!WALK) {
-                    const int i = lane + t * kWave;
-                    if (i < kTile * a.f) stage[i] = v[t];
-                } else {
-                    if (lane < a.f) stage[t * a.f + lane] = v[t];
-                }
+            for (int t = 0; t < kStageIt; ++t) {
+                const int i = lane + t * kWave;
+                if (i < nf) stage[i] = v[t];
             }
+            __syncthreads();
+        } else if constexpr (kStage) {
+            // f <= f_pad <= 64: lane j holds factor j of row t
+            const int rows = tile.z - ub * kTile;     // users of this block (may be <= 0)
+            const int mine = (lane < rows && lane < kTile) ? a.sorted_users[tile.y + ub * kTile + lane] : 0;
+            float v[kTile];
+#pragma unroll
+            for (int t = 0; t < kTile; ++t) {
+                const int ut = __builtin_amdgcn_readlane(mine, t);
+                v[t] = (t < rows && lane < a.f) ? a.U[(int64_t)ut * a.f + lane] : 0.0f;
+            }
+            __syncthreads();                          // the previous block's reads are done
+#pragma unroll
+            for (int t = 0; t < kTile; ++t)
+                if (lane < a.f) stage[t * a.f + lane] = v[t];
             __syncthreads();
         }
         auto ux = [&](int j) __attribute__((always_inline)) -> float {
@@ -802,19 +801,34 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
         // a false sweep: every user stopped after tile b (two blocks or
         // fewer) or after tile b - 1 (rotated blocks)
         constexpr int kStopLag = UB <= 2 ? 1 : 0;
-        if constexpr (MODE == kSweepBrute && UB > 2) {
-            // No stop test: the loop runs while both tiles of a pair exist
-            // and an odd last tile is swept after it.  An exit between the
-            // halves would give the wait-count analysis a path on which the
-            // first half's operand loads are the newest at the loop head,
-            // which then waits for every load in flight (the two-tile
-            // prefetch lost on every other tile).
+        if constexpr (MODE != kSweepWalk) {
+            // The loop runs while both tiles of a pair exist, every path
+            // through its body passes both halves, and an odd last tile is
+            // swept after it.  An exit between the halves gives the
+            // wait-count analysis a path on which the first half's operand
+            // loads are the newest at the loop head, which then waits for
+            // every load in flight (the two-tile prefetch lost on every
+            // other tile).  A stop after the first half (norm-pruned sweep)
+            // takes effect after the second, whose tile then finds no active
+            // user: no hit and no state change, one tile of products spent
+            // out of hundreds.  The walk, a few tiles long, keeps the exit.
             int b = b0;
-            for (; b + 1 < n_blk; b += 2) {
-                sweep(b, std::integral_constant<int, 0>{});
-                sweep(b + 1, std::integral_constant<int, 1>{});
+            if constexpr (MODE == kSweepBrute) {
+                for (; b + 1 < n_blk; b += 2) {
+                    sweep(b, std::integral_constant<int, 0>{});
+                    sweep(b + 1, std::integral_constant<int, 1>{});
+                }
+                if (b < n_blk) sweep(b, std::integral_constant<int, 0>{});
+            } else {
+                for (; b + 1 < n_blk; b += 2) {
+                    const bool live0 = sweep(b, std::integral_constant<int, 0>{});
+                    const bool live1 = sweep(b + 1, std::integral_constant<int, 1>{});
+                    if (!live0) { b_done = b + kStopLag; break; }
+                    if (!live1) { b_done = b + 1 + kStopLag; break; }
+                }
+                if (b_done == n_blk && b < n_blk && !sweep(b, std::integral_constant<int, 0>{}))
+                    b_done = b + kStopLag;
             }
-            if (b < n_blk) sweep(b, std::integral_constant<int, 0>{});
         } else {
             for (int b = b0; b < n_blk; b += 2) {
                 if (!sweep(b, std::integral_constant<int, 0>{})) { b_done = b + kStopLag; break; }
