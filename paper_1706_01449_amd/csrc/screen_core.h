@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
         int itm[2] = {-1, -1}, scl[2] = {127, 127};
         float2 cgx[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};
         floatx16_t acc[2];
-        int itP = -1;                 // the previous tile's item, bound and norms
+        int itP = -1;                 // the previous tile's item and norms
         float2 cgP = make_float2(0.0f, 0.0f);
         load_tile(b0, ops[0], itm[0], scl[0], cgx[0]);
         load_tile(b0 + 1 < n_blk ? b0 + 1 : b0, ops[1], itm[1], scl[1], cgx[1]);
