@@ -235,6 +235,28 @@ def test_norm_pruned_small(prec, shape):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("f", [50, 100])
+@pytest.mark.parametrize("n_i", [417, 449, 800, 801, 1025])
+def test_sweep_tile_count_parity(prec, f, n_i):
+    """The sweep takes tiles in pairs and an odd last tile alone: both
+    parities of the tile count left after the warm-up (14, 15, 25, 26, 33
+    tiles), for the brute force (four user blocks per wave in bfloat16 at
+    f = 50, two at f = 100, one in float32 at f = 100) and the norm-pruned
+    sweep, return the oracle's answer; 300 users leave a partial block."""
+    import paper_1706_01449_amd as mips
+    import torch
+    from gpu_util import to_dev
+    log(f"tile-count parity n_i={n_i} f={f} prec={prec}")
+    U, I = mipsgen.generate("mf", 21, n_users=300, n_items=n_i, f=f)
+    idx, score = gpu_topk(U, I, 10, prec)
+    assert_parity(idx, score, U, I, 10)
+    Ut, It = to_dev(U, I)
+    pidx, psc = mips.norm_pruned_topk(Ut, It, 10, prec)
+    torch.cuda.synchronize()
+    assert_parity(pidx.cpu().numpy(), psc.cpu().numpy(), U, I, 10)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_norm_pruned_mf_full_size(prec):
     """480,000 x 17,770, f = 50, K = 10: every user's answer equals the
     oracle's, with fewer items scored than the brute force."""
