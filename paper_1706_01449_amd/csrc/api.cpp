@@ -432,12 +432,11 @@ int mips_topk_backward_noalloc(const float* U, const float* I, int64_t n_u, int6
 size_t mips_bmm_topk_workspace_size(int64_t n_u, int64_t n_i, int32_t f, int32_t K,
                                     int32_t precision) {
     if (check_common(n_u, n_i, f, K, precision) != MIPS_OK) return 0;
-    // one size for both sweeps (their plans may hold different block counts)
-    const int sp = screen_prec(precision);
-    ScreenPlan p0, p1;
-    make_screen_plan(n_u, n_i, f, K, sp, false, &p0);
-    make_screen_plan(n_u, n_i, f, K, sp, true, &p1);
-    return std::max(bmm_layout(p0).total, bmm_layout(p1).total);
+    // one plan for both sweeps (the norm-pruned one takes the brute force's
+    // user blocks per wave)
+    ScreenPlan p;
+    make_screen_plan(n_u, n_i, f, K, screen_prec(precision), false, &p);
+    return bmm_layout(p).total;
 }
 
 int mips_debug_set(int32_t knob, int32_t value) {
@@ -464,7 +463,8 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
     const bool casc = cascade_of(precision);
     precision = screen_prec(precision);
     ScreenPlan p;
-    make_screen_plan(n_u, n_i, f, K, precision, prune != 0, &p);
+    // the norm-pruned sweep takes the brute force's user blocks per wave
+    make_screen_plan(n_u, n_i, f, K, precision, false, &p);
     const BmmLayout L = bmm_layout(p);
     if (!workspace || workspace_bytes < L.total)
         return fail(MIPS_ERR_WORKSPACE, "workspace needs %zu bytes (got %zu)", L.total, workspace_bytes);

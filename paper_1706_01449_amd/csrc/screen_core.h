@@ -1075,8 +1075,8 @@ static hipError_t go_screen(const ScreenPlan& p, const ScreenArgs& a, hipStream_
         if (p.UB != UBS) return hipErrorInvalidValue;   // plan and kernel disagree
         screen_kernel<PREC, KM, NCH, UBS, kSweepWalk><<<grid, blk, 0, s>>>(a, a.cblockmax);
     } else if (a.prune) {
-        if (p.UB != UBS) return hipErrorInvalidValue;
-        screen_kernel<PREC, KM, NCH, UBS, kSweepPruned><<<grid, blk, 0, s>>>(a, a.blockmax);
+        if (p.UB != UBB) return hipErrorInvalidValue;
+        screen_kernel<PREC, KM, NCH, UBB, kSweepPruned><<<grid, blk, 0, s>>>(a, a.blockmax);
     } else {
         if (p.UB != UBB) return hipErrorInvalidValue;
         screen_kernel<PREC, KM, NCH, UBB, kSweepBrute><<<grid, blk, 0, s>>>(a, a.blockmax);
