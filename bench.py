@@ -34,6 +34,35 @@ SCREEN_SOURCES = ["include/mips.h", "paper_1706_01449_amd/csrc/internal.h",
 TRAFFIC_FILE = "profiles/screen_kernel_mf_480000x17770_f50_bf16_K10_traffic.txt"
 
 
+def precision_only(prec, steps, warmup):
+    """The precision workload alone, one screen precision: calls timed with
+    HIP events, for counter passes on its screen and certification kernels."""
+    import torch
+    import mipsgen
+    import paper_1706_01449_amd as mips
+    dev = torch.device("cuda:0")
+    U, I = mipsgen.generate("precision", 0)
+    Ut = torch.from_numpy(U).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    ws = torch.empty(mips.lib().mips_bmm_topk_workspace_size(U.shape[0], I.shape[0], U.shape[1], 10,
+                                                              mips.PRECISIONS[prec]),
+                     dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        mips.bmm_topk(Ut, It, 10, prec, workspace=ws)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        mips.bmm_topk(Ut, It, 10, prec, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms.sort()
+    print(json.dumps({"workload": "precision_1000000x136000_f100_K10", "precision": prec,
+                      "calls": steps, "ms_per_call_median": ms[len(ms) // 2]}), flush=True)
+
+
 def screen_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -385,6 +414,10 @@ def main():
     ap.add_argument("--maximus-build", default="", metavar="C,C,...",
                     help="only time Maximus index builds on the clustered workload at these "
                          "cluster counts (one JSON line each) and exit")
+    ap.add_argument("--precision-only", default="", metavar="PREC",
+                    help="only run the 1,000,000 x 136,000 (f = 100, K = 10) workload with this "
+                         "screen precision for --steps calls after --warmup, print one JSON line "
+                         "and exit (the command the per-kernel counter passes profile)")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the screen kernel sources and exit")
     args = ap.parse_args()
@@ -396,6 +429,9 @@ def main():
         return
     if args.maximus_build:
         maximus_build_only([int(c) for c in args.maximus_build.split(",")], args.steps, args.warmup)
+        return
+    if args.precision_only:
+        precision_only(args.precision_only, args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
