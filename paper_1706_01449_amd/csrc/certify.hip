@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             unorm = sqrt(unorm);
         }
         // the user's two lists (lanes n and n+32 of its screen wave)
-        const int64_t base0 = cand_at(ublk, n, 0, a.cap), base1 = cand_at(ublk, n + 32, 0, a.cap);
+        const int64_t base0 = cand_base(ublk, n, a.cap, a.cand_lm), base1 = cand_base(ublk, n + 32, a.cap, a.cand_lm);
+        const int cst = cand_stride(a.cand_lm);
         for (int j0 = g; j0 < tot; j0 += 4 * G) {
             int2 e[4];
             float Ci[4], Gi[4];
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(256) certify_kernel(const ScreenArgs a, int UB
             for (int q = 0; q < 4; ++q) {
                 const int j = j0 + q * G;
                 e[q] = make_int2(0, -1);
-                if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * kCandStride : base1 + (j - m0) * kCandStride];
+                if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * cst : base1 + (j - m0) * cst];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) e[q].y = cand_item(a, e[q].y);
@@ -266,7 +267,8 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     double tau64 = (double)us.w;       // kept pairs: key >= tau64
     float thr = us.w;                  // candidates: upper bound >= thr (thr <= tau64)
     const int tot = c0 + c1;
-    const int64_t base0 = cand_at(ublk, n, 0, a.cap), base1 = cand_at(ublk, n + 32, 0, a.cap);
+    const int64_t base0 = cand_base(ublk, n, a.cap, a.cand_lm), base1 = cand_base(ublk, n + 32, a.cap, a.cand_lm);
+    const int cst = cand_stride(a.cand_lm);
     __syncthreads();
     double unorm = 0.0;   // ||u||, for the relative error statistic only
     if (a.want_stats) {
@@ -473,7 +475,7 @@ __global__ void __launch_bounds__(64) certify_wave_kernel(const ScreenArgs a, in
     for (int base = 0; base < tot; base += 64) {
         const int j = base + lane;
         int2 e = make_int2(0, -1);
-        if (j < tot) e = a.cand[(j < c0) ? base0 + j * kCandStride : base1 + (j - c0) * kCandStride];
+        if (j < tot) e = a.cand[(j < c0) ? base0 + j * cst : base1 + (j - c0) * cst];
         e.y = cand_item(a, e.y);
         bool keep = false;
         if (e.y >= 0) {

@@ -40,15 +40,20 @@ __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap, bool sto
                       : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1)));
 }
 
-// Candidate lists, element-major: entry j of lane l of user block blk sits
-// at (blk cap + j) 64 + l (each lane appends to a list of its own; the j-th
-// entries of a block's 64 lanes are contiguous, so a wave reading one entry
-// per lane reads 512 contiguous bytes).  Entries of one lane are
-// kCandStride apart.
+// Candidate lists: each lane of a screen wave appends to a list of its own
+// (cap entries).  Element-major (FP32, BF16): entry j of lane l of user
+// block blk sits at (blk cap + j) 64 + l, so the j-th entries of a block's 64
+// lanes are contiguous and the fused certification, one lane per user,
+// reads 512 contiguous bytes per entry.  Lane-major (E4M3, whose lists run
+// to hundreds of entries): at (blk 64 + l) cap + j, so a lane's stores fill
+// its own cache lines and the certification wave that reads one user's list
+// 64 entries at a time reads contiguous memory.  cand_base gives entry 0 of
+// a lane's list; entry j is cand_stride entries further on.
 constexpr int kCandStride = 64;
-__host__ __device__ inline int64_t cand_at(int64_t blk, int lane, int j, int cap) {
-    return ((blk * cap + j) << 6) + lane;
+__host__ __device__ inline int64_t cand_base(int64_t blk, int lane, int cap, bool lane_major) {
+    return lane_major ? ((blk << 6) + lane) * cap : ((blk * cap) << 6) + lane;
 }
+__host__ __device__ inline int cand_stride(bool lane_major) { return lane_major ? 1 : kCandStride; }
 inline size_t cand_bytes(int64_t n_ublk, int cap) { return (size_t)n_ublk * 64 * cap * 8; }
 
 
@@ -139,6 +144,7 @@ struct ScreenArgs {
     float4* uscal;            // n_u: (A_u, B_u, slack_u, tau_u)
     int64_t n_ublk;           // user blocks with candidate storage
     int* cnt;                 // n_ublk * 64 candidate counts
+    int cand_lm;              // candidate lists lane-major (the E4M3 screen) or element-major
     int2* cand;               // n_ublk * 64 lists of cap candidates (score bits, reference):
                               // the reference is the item (walk) or the sorted position
                               // (brute force), see cand_item

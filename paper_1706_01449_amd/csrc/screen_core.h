@@ -632,6 +632,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
     // min(count, cap - 1): a list that overflows sends its user to the exact
     // path, whatever its last slot holds.
     const int lane_slot0 = lane;
+    constexpr bool kCandLM = PREC == PREC_FP8;   // candidate list layout (lane-major for E4M3)
     auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 cg)
         __attribute__((always_inline)) {
         // the tile's bound maxima, read (scalar load) where they are used: a
@@ -685,8 +686,8 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
                     }
                     if (hit) {
                         list_insert(L, lb);
-                        int2* const cb = a.cand + cand_at(w * UB + ub, 0, 0, a.cap);
-                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * kCandStride] =
+                        int2* const cb = a.cand + cand_base(w * UB + ub, lane_slot0, a.cap, kCandLM);
+                        cb[(cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * cand_stride(kCandLM)] =
                             make_int2(__float_as_int(v), ref);
                         cnt[ub] += 1;
                     }
@@ -862,12 +863,12 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
 #pragma unroll
                 for (int r = 2; r < 16; r += 2) m = vmax(m, vmax(v[r], v[r + 1]));
                 if (!ballot(m >= thr)) continue;
-                int2* const cb = a.cand + cand_at(w * UB + ub, 0, 0, a.cap);
+                int2* const cb = a.cand + cand_base(w * UB + ub, lane_slot0, a.cap, kCandLM);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = 8 * (r >> 2) + 4 * h + (r & 3);
                     if (v[r] >= thr && row < rem) {
-                        cb[lane_slot0 + (cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * kCandStride] =
+                        cb[(cnt[ub] < a.cap ? cnt[ub] : a.cap - 1) * cand_stride(kCandLM)] =
                             make_int2(__float_as_int(v[r]), b * kTile + row);
                         cnt[ub] += 1;
                     }
@@ -910,8 +911,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
             bool bad = (cA > cap) || (cB > cap);
             const int tot = m0 + m1;
             // the user's two lists (its lane n and lane n + 32 halves)
-            const int64_t base0 = cand_at(w * UB + ubl, n, 0, cap);
-            const int64_t base1 = cand_at(w * UB + ubl, n + 32, 0, cap);
+            const int64_t base0 = cand_base(w * UB + ubl, n, cap, kCandLM);
+            const int64_t base1 = cand_base(w * UB + ubl, n + 32, cap, kCandLM);
+            constexpr int cst = kCandLM ? 1 : kCandStride;
             const float* urow = a.U + u * a.f;
             double tau64 = (double)ut;   // kept pairs: key >= tau64
             float thr = ut;              // rescored pairs: upper bound >= thr (<= tau64)
@@ -932,7 +934,7 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
                 for (int q = 0; q < 8; ++q) {
                     const int j = j0 + q;
                     e[q] = make_int2(0, -1);
-                    if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * kCandStride : base1 + (j - m0) * kCandStride];
+                    if (j < tot) e[q] = a.cand[(j < m0) ? base0 + j * cst : base1 + (j - m0) * cst];
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
