@@ -571,7 +571,7 @@ static int bmm_impl(const float* U, int64_t n_u, const float* I, int64_t n_i, in
         a.n_ublk = p.n_ublk;
         a.cnt = (int*)(ws + L.cnt);
         a.cand = (int2*)(ws + L.cand);
-        a.cand_lm = p.prec == PREC_FP8;      // the layout the screen kernel writes
+        a.cand_lm = !fused_certify(p.prec, p.KM, p.UB);      // the layout the screen kernel writes
         {
             PhaseTimer t(MIPS_PHASE_SCREEN, s);
             if ((e = launch_screen(p, a, s)) != hipSuccess) return hip_fail(e, "screen");

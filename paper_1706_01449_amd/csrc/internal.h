@@ -40,15 +40,26 @@ __host__ __device__ constexpr int ub_for(int prec, int km, int nch_cap, bool sto
                       : (km <= 16 ? 2 : ((km <= 32 && !(prec == PREC_BF16 && nch_cap >= 8)) ? 2 : 1)));
 }
 
+// Certification runs at the end of the screen kernel when the K-list fits a
+// small sorted register list, an even number of user blocks keeps every lane
+// busy (one user per lane and pass), and the screen keeps few candidates per
+// user (not E4M3, whose hundreds of candidates per user make one lane per
+// user too slow; there the separate kernel spreads a user over 16 or 64
+// lanes).
+__host__ __device__ constexpr bool fused_certify(int prec, int km, int ub) {
+    return prec != PREC_FP8 && km <= 16 && ub % 2 == 0;
+}
+
 // Candidate lists: each lane of a screen wave appends to a list of its own
-// (cap entries).  Element-major (FP32, BF16): entry j of lane l of user
-// block blk sits at (blk cap + j) 64 + l, so the j-th entries of a block's 64
-// lanes are contiguous and the fused certification, one lane per user,
-// reads 512 contiguous bytes per entry.  Lane-major (E4M3, whose lists run
-// to hundreds of entries): at (blk 64 + l) cap + j, so a lane's stores fill
-// its own cache lines and the certification wave that reads one user's list
-// 64 entries at a time reads contiguous memory.  cand_base gives entry 0 of
-// a lane's list; entry j is cand_stride entries further on.
+// (cap entries).  Element-major where the screen kernel certifies its own
+// users (FP32/BF16, K <= 16): entry j of lane l of user block blk sits at
+// (blk cap + j) 64 + l, so the j-th entries of a block's 64 lanes are
+// contiguous and the fused certification, one lane per user, reads 512
+// contiguous bytes per entry.  Lane-major where a certification kernel reads
+// them (E4M3, K > 16, one user block per wave): at (blk 64 + l) cap + j, so
+// a lane's stores fill its own cache lines and the kernel's lanes, reading
+// consecutive entries of one list, read contiguous memory.  cand_base gives
+// entry 0 of a lane's list; entry j is cand_stride entries further on.
 constexpr int kCandStride = 64;
 __host__ __device__ inline int64_t cand_base(int64_t blk, int lane, int cap, bool lane_major) {
     return lane_major ? ((blk << 6) + lane) * cap : ((blk * cap) << 6) + lane;

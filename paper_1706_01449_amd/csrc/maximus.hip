@@ -1431,7 +1431,7 @@ int walk_certify_fallback(const mips_maximus_index* ix, const ScreenPlan& p, int
     a.n_ublk = p.n_ublk;
     a.cnt = cnt;
     a.cand = cand;
-    a.cand_lm = p.prec == PREC_FP8;          // the layout the screen kernel writes
+    a.cand_lm = !fused_certify(p.prec, p.KM, p.UB);          // the layout the screen kernel writes
     a.out_idx = out_idx;
     a.out_score = out_score;
     if (p.fast) {

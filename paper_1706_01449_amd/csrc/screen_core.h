@@ -254,15 +254,6 @@ __host__ __device__ constexpr int warm_sets(int km) {
     return km <= 16 ? 2 : (km <= 32 ? 3 : 4);
 }
 
-// Certification runs at the end of the screen kernel when the K-list fits a
-// small sorted register list, an even number of user blocks keeps every lane
-// busy (one user per lane and pass), and the screen keeps few candidates per
-// user (not E4M3, whose hundreds of candidates per user make one lane per
-// user too slow; there the separate kernel spreads a user over 16 or 64
-// lanes).
-__host__ __device__ constexpr bool fused_certify(int prec, int km, int ub) {
-    return prec != PREC_FP8 && km <= 16 && ub % 2 == 0;
-}
 
 
 // ---------------------------------------------------------------------------
@@ -632,7 +623,9 @@ __global__ void __launch_bounds__(64) screen_kernel(const ScreenArgs a,
     // min(count, cap - 1): a list that overflows sends its user to the exact
     // path, whatever its last slot holds.
     const int lane_slot0 = lane;
-    constexpr bool kCandLM = PREC == PREC_FP8;   // candidate list layout (lane-major for E4M3)
+    // candidate list layout: element-major for the fused certification (one
+    // lane per user), lane-major for the certification kernels
+    constexpr bool kCandLM = !fused_certify(PREC, KM, UB);
     auto test_block = [&](int b, int ub, const floatx16_t& sc, int item, float2 cg)
         __attribute__((always_inline)) {
         // the tile's bound maxima, read (scalar load) where they are used: a
